@@ -1,0 +1,157 @@
+"""Closed-form results the integrator approximates, used to pin the oracle.
+
+Nothing here integrates a geodesic or calls the oracle: each function is a
+textbook closed form or a one-dimensional quadrature, so that agreement with
+the oracle is evidence about the oracle.
+
+* Kerr radial potential R(r) (Carter): a ray arriving from the observer is
+  captured iff R has no turning point between the horizon and the observer.
+* Bardeen's critical curve (the shadow boundary for an observer at infinity).
+* Schwarzschild orbit quadratures for the azimuthal sweep of a scattered ray
+  and for the radius where a face-on ray crosses the equatorial plane.
+* Circular-orbit kinematics of Bardeen, Press & Teukolsky (1972).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import integrate, optimize
+from scipy.spatial import cKDTree
+
+SQRT27 = np.sqrt(27.0)
+
+
+# --------------------------------------------------------------- horizons
+def r_horizon(a):
+    return 1.0 + np.sqrt(1.0 - a * a)
+
+
+def photon_orbit_radii(a):
+    """Prograde and retrograde equatorial circular photon orbits."""
+    r_pro = 2.0 * (1.0 + np.cos(2.0 / 3.0 * np.arccos(-a)))
+    r_ret = 2.0 * (1.0 + np.cos(2.0 / 3.0 * np.arccos(a)))
+    return r_pro, r_ret
+
+
+# ------------------------------------------------------------ radial potential
+def radial_potential_coeffs(a, lam, eta):
+    """R(r) = r^4 + (a^2 - lam^2 - eta) r^2 + 2 (eta + (lam - a)^2) r - a^2 eta,
+    for E = 1, lam = L/E, eta = Q/E^2 (coefficients, highest power first)."""
+    return np.array([1.0, 0.0, a * a - lam * lam - eta, 2.0 * (eta + (lam - a) ** 2), -a * a * eta])
+
+
+def captured_by_potential(a, lam, eta, r_start):
+    """True iff R(r) has no real root in (r_bh, r_start): the inbound ray then
+    meets no radial turning point and falls through the horizon."""
+    rbh = r_horizon(a)
+    roots = np.roots(radial_potential_coeffs(a, lam, eta))
+    real = roots[np.abs(roots.imag) < 1e-9 * np.maximum(1.0, np.abs(roots.real))].real
+    return not np.any((real > rbh) & (real < r_start))
+
+
+# --------------------------------------------------------------- critical curve
+def bardeen_curve(a, incl, n=400001):
+    """Points (alpha, beta >= 0) of the critical curve seen at inclination incl.
+    For a = 0 it is the circle of radius sqrt(27)."""
+    if a == 0.0:
+        t = np.linspace(0.0, np.pi, n)
+        return SQRT27 * np.cos(t), SQRT27 * np.sin(t)
+    r_pro, r_ret = photon_orbit_radii(a)
+    # cluster samples at the ends, where beta grows like sqrt(r - r_end)
+    u = np.linspace(0.0, np.pi, n)
+    r = r_pro + (r_ret - r_pro) * 0.5 * (1.0 - np.cos(u))
+    xi = -(r ** 3 - 3.0 * r ** 2 + a * a * r + a * a) / (a * (r - 1.0))
+    eta = -r ** 3 * (r ** 3 - 6.0 * r ** 2 + 9.0 * r - 4.0 * a * a) / (a * a * (r - 1.0) ** 2)
+    si, ci = np.sin(incl), np.cos(incl)
+    if si == 0.0:
+        keep = np.abs(xi) < 1e-3
+        rad = np.sqrt(np.maximum(eta[keep] + xi[keep] ** 2 + a * a, 0.0)).mean()
+        t = np.linspace(0.0, np.pi, n)
+        return rad * np.cos(t), rad * np.sin(t)
+    b2 = eta + a * a * ci * ci - xi * xi * (ci / si) ** 2
+    if ci == 0.0 or abs(ci) < 1e-15:
+        b2 = np.maximum(b2, 0.0)   # edge-on: the ends are exactly beta = 0
+    ok = b2 >= 0.0
+    return -xi[ok] / si, np.sqrt(b2[ok])
+
+
+def effective_impact(a, incl, E, L, Q):
+    """Asymptotic image-plane position (alpha, |beta|) of a ray with constants
+    E, L, Q, in the same convention as the critical curve."""
+    lam = L / E
+    eta = Q / (E * E)
+    si, ci = np.sin(incl), np.cos(incl)
+    if si == 0.0:
+        rad = np.sqrt(np.maximum(eta + lam * lam + a * a, 0.0))
+        return rad, np.zeros_like(rad)
+    alpha = -lam / si
+    beta = np.sqrt(np.maximum(eta + a * a * ci * ci - lam * lam * (ci / si) ** 2, 0.0))
+    return alpha, beta
+
+
+class CriticalBand:
+    """Distance from a ray's effective image-plane point to the critical curve."""
+
+    def __init__(self, a, incl):
+        self.a, self.incl = a, incl
+        al, be = bardeen_curve(a, incl)
+        self.tree = cKDTree(np.column_stack([al, be]))
+        self.pole_on = np.sin(incl) == 0.0
+        if self.pole_on:
+            self.radius = np.hypot(al[0], be[0])
+
+    def distance(self, E, L, Q):
+        al, be = effective_impact(self.a, self.incl, np.asarray(E), np.asarray(L), np.asarray(Q))
+        if self.pole_on:
+            return np.abs(al - self.radius)
+        d, _ = self.tree.query(np.column_stack([np.atleast_1d(al), np.atleast_1d(be)]))
+        return d
+
+
+# ------------------------------------------------------- Schwarzschild orbits
+def schw_turning_point(b):
+    """Largest root of r^3 - b^2 (r - 2) = 0 (closest approach), b > sqrt(27)."""
+    return optimize.brentq(lambda r: r ** 3 - b * b * (r - 2.0), 3.0, max(3.0 * b, 10.0))
+
+
+def schw_sweep(b, r_from, r_to=None, through_turning=True):
+    """Total orbital angle swept by a Schwarzschild null ray of impact parameter
+    b, moving in from r_from, through the turning point and out to r_to."""
+    def leg(r_hi, r_lo):
+        # u = 1/r; dpsi/du = 1 / sqrt(1/b^2 - u^2 + 2 u^3)
+        u_lo, u_hi = 1.0 / r_hi, 1.0 / r_lo
+        f = lambda u: 1.0 / np.sqrt(max(1.0 / (b * b) - u * u + 2.0 * u ** 3, 1e-300))
+        if through_turning:
+            # substitute u = u_hi - s^2 to remove the inverse-square-root end point
+            g = lambda s: 2.0 * s * f(u_hi - s * s)
+            val, _ = integrate.quad(g, 0.0, np.sqrt(u_hi - u_lo), epsabs=1e-14, epsrel=1e-13,
+                                    limit=400)
+            return val
+        val, _ = integrate.quad(f, u_lo, u_hi, epsabs=1e-14, epsrel=1e-13, limit=400)
+        return val
+
+    if not through_turning:
+        return leg(r_from, r_to)
+    rmin = schw_turning_point(b)
+    total = leg(r_from, rmin)
+    if r_to is not None:
+        total += leg(r_to, rmin)
+    return total
+
+
+# --------------------------------------------------- circular-orbit kinematics
+def kerr_circular_ut(a, r):
+    """u^t of a prograde equatorial circular geodesic (Bardeen, Press &
+    Teukolsky 1972)."""
+    return (r ** 1.5 + a) / (r ** 0.75 * np.sqrt(r ** 1.5 - 3.0 * r ** 0.5 + 2.0 * a))
+
+
+def kerr_circular_energy(a, r):
+    return (r ** 1.5 - 2.0 * r ** 0.5 + a) / (r ** 0.75 * np.sqrt(r ** 1.5 - 3.0 * r ** 0.5 + 2.0 * a))
+
+
+def isco_by_energy_minimum(a):
+    """r_ISCO as the minimum of the circular-orbit energy (no closed form used)."""
+    lo = photon_orbit_radii(a)[0] + 1e-6
+    res = optimize.minimize_scalar(lambda r: kerr_circular_energy(a, r), bounds=(lo, 12.0),
+                                   method="bounded", options={"xatol": 1e-12})
+    return res.x

@@ -1,0 +1,232 @@
+"""Pins of the oracle's integrator (Sec. 2): step-size rule, remap, Euler
+fallback, conservation, convergence order, termination, and the
+equatorial-crossing recorder.
+
+Exact trajectories that the scheme must reproduce step by step (radial
+infall, circular photon orbits) pin eq. (2) and eq. (3); Schwarzschild orbit
+quadratures and textbook circular-orbit kinematics pin the dynamics and the
+recorder; the paper's pole case pins the eq. (4) fallback.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import optimize
+
+import analytic
+from paper_1303_5057_amd import workloads as W
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+DS = GOLDEN["integrator_parameters"]["step_frac"]
+
+
+def _params(orc, **kw):
+    return orc.make_params(**kw)
+
+
+def test_step_rule_radial_infall(orc):
+    """Radial null infall in Schwarzschild keeps k^r constant, so the first
+    term of eq. (2) gives r_{n+1} = r_n (1 - Delta) while 2 Delta r < r - 2
+    (up to the RK4 truncation error of k^t feeding back through the null
+    condition). Near the horizon the second term takes over, the null monitor
+    of eq. (4) rejects the RK4 steps, and each Euler step of h/9 with
+    h = (r - 2) / (2 |k^r|) moves r - 2 by exactly -(r - 2) / 18."""
+    x0 = orc.camera(0.0, 1000.0, np.pi / 2, 0.0, 0.0)
+    assert x0[6] == 0.0 and x0[7] == 0.0
+    st, path, fl = orc.trace_path(_params(orc), 0.0, x0)
+    assert st == orc.CAPTURED
+    r = np.concatenate([[x0[1]], path[:, 1]])
+    far = n_euler_near = 0
+    for k in range(len(path)):
+        if r[k] > 3.0:
+            assert r[k + 1] == pytest.approx(r[k] * (1 - DS), rel=1e-6)
+            assert path[k, 5] == pytest.approx(x0[5], rel=1e-6)
+            far += 1
+        elif 2 * DS * r[k] > r[k] - 2 and fl[k] & 1:
+            assert r[k + 1] - 2 == pytest.approx((r[k] - 2) * 17 / 18, rel=1e-10)
+            n_euler_near += 1
+    assert far > 170 and n_euler_near > 20
+
+
+def _circular_state(kind):
+    """a = 0 photon sphere r = 3: equatorial (kind='phi') or polar (kind='theta')
+    orbit; null condition -(1/3) kt^2 + 9 k_ang^2 = 0."""
+    kt = -1.0
+    w = 1.0 / np.sqrt(27.0)
+    if kind == "phi":
+        return np.array([0.0, 3.0, np.pi / 2, 0.0, kt, 0.0, 0.0, -w])
+    return np.array([0.0, 3.0, np.pi / 2, 0.0, kt, 0.0, w, 0.0])
+
+
+def test_step_rule_azimuthal_term(orc):
+    """On the circular photon orbit only |dphi/dl| enters eq. (2): each step
+    advances phi by exactly Delta."""
+    p = _params(orc, max_steps=150)
+    st, path, fl = orc.trace_path(p, 0.0, _circular_state("phi"))
+    assert st == orc.UNFINISHED and len(path) == 150
+    n = np.arange(1, 151)
+    assert np.allclose(path[:, 3], -n * DS, rtol=0, atol=1e-11)
+    assert np.allclose(path[:, 1], 3.0, rtol=0, atol=1e-10)
+    assert not np.any(fl)
+
+
+def test_remap_on_polar_circular_orbit(orc):
+    """Polar photon orbit through both poles: theta advances by Delta per step
+    (the |dtheta/dl| term of eq. 2); whenever it leaves [0, pi] the remap of
+    eq. (3) reflects theta, shifts phi by +-pi and flips k^theta."""
+    nstep = int(2.2 * np.pi / DS)
+    p = _params(orc, max_steps=nstep)
+    st, path, fl = orc.trace_path(p, 0.0, _circular_state("theta"))
+    psi = np.pi / 2 + DS * np.arange(1, nstep + 1)          # unwrapped polar angle
+    folded = np.mod(psi, 2 * np.pi)
+    theta = np.where(folded <= np.pi, folded, 2 * np.pi - folded)
+    assert np.allclose(path[:, 2], theta, rtol=0, atol=1e-10)
+    crossings = np.nonzero(np.diff(np.floor(psi / np.pi)))[0] + 1   # steps that left [0, pi]
+    assert list(np.nonzero(fl & 2)[0]) == list(crossings)
+    assert len(crossings) == 2
+    # phi: +pi at the first (theta > pi) remap, -pi at the second (theta < 0)
+    assert np.allclose(path[crossings[0]:crossings[1], 3], np.pi, atol=1e-12)
+    assert np.allclose(path[crossings[1]:, 3], 0.0, atol=1e-12)
+    # k^theta flips sign at each remap
+    sgn = np.sign(path[:, 6])
+    assert list(np.nonzero(np.diff(sgn))[0] + 1) == list(crossings)
+    assert not np.any(fl & 1)
+
+
+def test_euler_fallback_reintegrates_from_step_start(orc):
+    """With epsilon below any rounding residual, every step takes the eq. (4)
+    fallback: one forward-Euler step of h / 9 from the start of the step."""
+    a = 0.7
+    x = orc.camera(a, 1000.0, 1.2, 4.0, -3.0)
+    for _ in range(40):
+        x, _, _ = orc.step(_params(orc), a, x)
+    h = orc.step_size(orc.horizon(a), DS, x)
+    xn, fl, h_used = orc.step(_params(orc, xi_eps=1e-300), a, x)
+    assert fl & 1 and h_used == h
+    assert np.array_equal(xn, x + (h / 9.0) * orc.rhs(a, x))
+
+
+@pytest.mark.parametrize("phi0_deg", [0.0, 37.0, 123.0, 211.0, 300.0])
+def test_pole_case_from_the_paper(orc, phi0_deg):
+    """Sec. 2 pole test: a = 0.99, r0 cos(theta0) = 1000 M, r0 sin(theta0) =
+    4.833605 M. The production scheme carries the ray across both poles and
+    into the horizon, for any phi0. Its L_z is ~0 and its impact parameter is
+    inside the L_z = 0 critical value (closed form), so capture is the exact
+    outcome."""
+    g = GOLDEN["pole_case"]
+    cam = W.pole_camera(np.radians(phi0_deg))
+    assert cam.a == g["a"]
+    x0 = orc.camera(cam.a, cam.r_obs, cam.incl, cam.alpha_lo, cam.beta_lo)
+    assert x0[1] * np.cos(x0[2]) == pytest.approx(g["r0_cos_theta0"], rel=1e-12)
+    assert x0[1] * np.sin(x0[2]) == pytest.approx(g["r0_sin_theta0"], rel=1e-12)
+    assert np.mod(x0[3] - np.radians(phi0_deg) + np.pi, 2 * np.pi) == pytest.approx(np.pi, abs=1e-12)
+    E, L, Q = orc.conserved(cam.a, x0)
+    assert abs(L) < 1e-6
+    assert analytic.captured_by_potential(cam.a, L / E, Q / E ** 2, x0[1])
+    r = orc.trace(_params(orc), cam.a, x0)
+    assert r.status == orc.CAPTURED
+    assert r.n_remap >= 2
+    assert r.n_euler >= 1
+
+
+def _equatorial_escape(orc, b, ds=DS):
+    x0 = orc.camera(0.0, 1000.0, np.pi / 2, b, 0.0)
+    r = orc.trace(_params(orc, step_frac=ds), 0.0, x0)
+    E, L, Q = orc.conserved(0.0, x0)
+    bb = np.sqrt(L * L + Q) / E
+    return x0, r, bb
+
+
+@pytest.mark.parametrize("b", [6.0, 7.5, 10.0, 16.0])
+def test_escape_sweep_matches_schwarzschild_quadrature(orc, b):
+    """Total azimuth swept by a scattered equatorial ray equals the orbit
+    integral through the turning point, evaluated at the oracle's own end
+    radius; RK4 at Delta = 1/32 is accurate to a few 1e-6 rad even close to
+    the photon sphere."""
+    x0, r, bb = _equatorial_escape(orc, b)
+    assert r.status == orc.ESCAPED
+    exact = analytic.schw_sweep(bb, x0[1], r.x[1])
+    assert abs(abs(r.x[3] - x0[3]) - exact) < 1e-5
+
+
+def test_rk4_fourth_order_convergence(orc):
+    """Halving Delta divides the sweep error by ~2^4 (Richardson)."""
+    errs = []
+    for ds in (1 / 16, 1 / 32, 1 / 64):
+        x0, r, bb = _equatorial_escape(orc, 7.0, ds)
+        errs.append(abs(abs(r.x[3] - x0[3]) - analytic.schw_sweep(bb, x0[1], r.x[1])))
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 10.0 < e1 / e2 < 24.0
+
+
+def test_conservation_kerr(orc):
+    """E, L_z, Carter's Q and the null condition are conserved along Kerr rays
+    (a = 0.99, edge-on); RK4 keeps the drift of scattered rays below 1e-6."""
+    a = 0.99
+    for al, be in [(-6.0, 1.0), (9.0, -2.0), (3.0, 7.0), (-4.0, -6.5), (7.5, 0.5)]:
+        x0 = orc.camera(a, 1000.0, np.pi / 2, al, be)
+        c0 = orc.conserved(a, x0)
+        r = orc.trace(_params(orc), a, x0)
+        assert r.status == orc.ESCAPED
+        c1 = orc.conserved(a, r.x)
+        dE, dL, dQ = orc.drift(c0[0], c0[1], c0[2], c1[0], c1[1], c1[2])
+        assert max(dE, dL, dQ) < 1e-6
+        assert orc.xi(a, r.x) == pytest.approx(-1.0, abs=1e-6)
+
+
+def test_termination_rules(orc):
+    a = 0.5
+    x0 = orc.camera(a, 1000.0, 1.0, 2.0, 1.0)
+    assert x0[1] > 1000.0   # starts beyond r_escape, moving inward: not escaped
+    r = orc.trace(_params(orc, max_steps=37), a, x0)
+    assert r.status == orc.UNFINISHED and r.steps == 37
+    r = orc.trace(_params(orc), a, x0)
+    assert r.status == orc.CAPTURED and r.x[1] < orc.horizon(a) * 1.001
+    x0 = orc.camera(a, 1000.0, 1.0, 12.0, 1.0)
+    r = orc.trace(_params(orc), a, x0)
+    assert r.status == orc.ESCAPED and r.x[1] > 1000.0 and r.x[5] > 0.0
+    bad = x0.copy()
+    bad[5] = np.nan
+    r = orc.trace(_params(orc), a, bad)
+    assert r.status == orc.NONFINITE
+
+
+def test_isco_and_disk_redshift_closed_forms(orc):
+    assert orc.r_isco(0.0) == pytest.approx(6.0, rel=1e-15)
+    for a in (0.3, 0.9375, 0.99):
+        assert orc.r_isco(a) == pytest.approx(analytic.isco_by_energy_minimum(a), abs=1e-6)
+        for rc in (orc.r_isco(a), 9.0, 30.0):
+            E, L = 0.98, -2.5
+            om = 1 / (rc ** 1.5 + a)
+            ref = 1 / (analytic.kerr_circular_ut(a, rc) * (1 - om * L / E))
+            assert orc.disk_redshift(a, rc, E, L) == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("b", [5.5, 7.0, 10.0, 20.0])
+def test_disk_crossing_face_on_schwarzschild(orc, b):
+    """Face-on (i = 0) rays stay in a meridional plane; they cross the equator
+    on the inbound leg where the swept angle reaches pi/2 - theta0 (orbit
+    quadrature). The recorder interpolates linearly between steps, so it
+    agrees to the interpolation error; g = sqrt(1 - 3/r_c) since L = 0."""
+    x0 = orc.camera(0.0, 1000.0, 0.0, 0.0, b)
+    E, L, Q = orc.conserved(0.0, x0)
+    bb = np.sqrt(L * L + Q) / E
+    target = np.pi / 2 - x0[2]
+    rmin = analytic.schw_turning_point(bb)
+    rc = optimize.brentq(lambda r: analytic.schw_sweep(bb, x0[1], r, through_turning=False) - target,
+                         rmin * (1 + 1e-9), 900.0, xtol=1e-13)
+    res = orc.trace(_params(orc, record_disk=True, disk_rmin=0.0, disk_rmax=100.0), 0.0, x0)
+    assert res.disk[0] == pytest.approx(rc, rel=2e-3)
+    assert res.disk[2] == pytest.approx(np.sqrt(1 - 3 / res.disk[0]), rel=1e-10)
+    # a window that no crossing falls in records nothing
+    res = orc.trace(_params(orc, record_disk=True, disk_rmin=500.0, disk_rmax=600.0), 0.0, x0)
+    assert np.all(res.disk == 0.0)
+
+
+def test_printed_spins():
+    """The three spins printed with Fig. 6 are a_j = 1 - 10^(-j/5) for j = 1, 8, 15."""
+    g = GOLDEN["spins_printed"]
+    a = 1 - 10 ** (-np.arange(16) / 5)
+    for v in g["printed"]:
+        assert np.min(np.abs(a - v)) < 5e-7
