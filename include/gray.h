@@ -1,0 +1,187 @@
+/*
+ * gray.h -- C ABI of the MI355X (gfx950) Kerr photon-geodesic integrator.
+ *
+ * The library traces null geodesics of the Kerr spacetime backwards from an
+ * image plane, one independent photon per GPU lane, with the scheme of
+ * Chan, Psaltis & Ozel (2013), "GRay", Sec. 2: classical fourth-order
+ * Runge-Kutta on the second-order geodesic equations in Boyer-Lindquist
+ * coordinates (G = c = M = 1), the adaptive step of eq. (2), the horizon stop,
+ * the theta remap of eq. (3) and the null-condition monitor of eq. (4) with
+ * its forward-Euler re-integration at h/9.
+ *
+ * Conventions shared by every entry point
+ *   - All functions are C linkage, never throw, and return a gray_err code.
+ *   - Device buffers are allocated and freed by the caller; the library never
+ *     allocates device or host memory. Camera and parameter structs are host
+ *     memory and are consumed before the call returns (they travel as kernel
+ *     arguments), so the caller may reuse them immediately.
+ *   - Every call enqueues work on `hip_stream` (a hipStream_t; NULL = the
+ *     null stream) and returns without synchronising. Calls on different
+ *     streams with disjoint buffers and workspaces are independent. Two calls
+ *     that share a workspace must be ordered by the caller.
+ *   - Argument errors are detected on the host before anything is enqueued
+ *     and return GRAY_EINVAL (nothing is touched). A failed launch returns
+ *     GRAY_EDEVICE; gray_strerror() then describes it. Numerical failure is
+ *     per photon (status GRAY_NONFINITE), never a call error.
+ *   - n == 0 is valid and enqueues nothing.
+ *
+ * Photon state (gray_state), structure of arrays in device memory
+ *   x      component-major, 8 rows of `stride` elements:
+ *          row c holds component c of every photon, c = 0..7 for
+ *          (t, r, theta, phi, k^t, k^r, k^theta, k^phi); element type is
+ *          double for GRAY_FP64 and float (the high word) for GRAY_FP32C.
+ *          k is the integrated tangent; the photon's physical momentum is
+ *          p = -k (the ray is traced from the observer back to the hole).
+ *   lo     GRAY_FP32C only: float compensation words, same shape as x; the
+ *          state is hi + lo. Must be NULL for GRAY_FP64.
+ *   status int32[n]  gray_status of each photon.
+ *   steps  int32[n]  accepted steps taken so far.
+ *   cam    int32[n]  camera index of each photon (written by camera_init).
+ *   counters  optional int32, 3 rows of `stride`: Euler fallbacks (eq. 4),
+ *          theta remaps (eq. 3), steps taken in FP64 (GRAY_FP32C; 0 else).
+ *   mark   optional double, 8 rows of `stride`: the last accepted state with
+ *          r >= 2 r_bh before the photon last fell below 2 r_bh (drift
+ *          diagnostics for captured photons; r = 0 if never marked).
+ *   disk   optional double, 3 rows of `stride`: first equatorial crossing
+ *          inside the recorder window (r_c, phi_c, redshift g); all zero
+ *          when there was none. Required when GRAY_RECORD_DISK is set.
+ *   stride must be >= n and a multiple of 64; all rows are stride apart.
+ */
+#ifndef GRAY_H
+#define GRAY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GRAY_OK = 0,
+    GRAY_EINVAL = -1,       /* bad argument; nothing was enqueued            */
+    GRAY_EDEVICE = -2,      /* HIP runtime or launch failure                 */
+    GRAY_EWORKSPACE = -3,   /* workspace NULL or smaller than required       */
+    GRAY_EUNSUPPORTED = -4  /* valid request this build cannot serve         */
+} gray_err;
+
+typedef enum {
+    GRAY_FP64 = 0,  /* all arithmetic in double                               */
+    GRAY_FP32C = 1  /* float stages, compensated (hi + lo) state update, and
+                       double steps near the horizon and turning points       */
+} gray_precision;
+
+typedef enum {
+    GRAY_RUNNING = 0,    /* still integrating (resumable)                     */
+    GRAY_CAPTURED = 1,   /* r < r_bh (1 + horizon_eps): horizon stop, Sec. 2  */
+    GRAY_ESCAPED = 2,    /* r > r_escape while moving outward                 */
+    GRAY_UNFINISHED = 3, /* max_steps reached                                 */
+    GRAY_NONFINITE = 4   /* non-finite state or step size                     */
+} gray_status;
+
+/* gray_params.flags */
+#define GRAY_RECORD_DISK 1u /* record the first equatorial crossing (Sec. 3) */
+
+/* One camera: a Kerr hole of spin a seen from distance r_obs at inclination
+ * incl (radians from the spin axis, azimuth 0), with a regular cell-centred
+ * nx * ny grid on a flat image plane perpendicular to the line of sight
+ * (Sec. 2 and Sec. 3 place the image plane at r = 1000 M). Pixel (ix, iy) has
+ *   alpha = alpha_lo + (alpha_hi - alpha_lo) (ix + 1/2) / nx   (along +phi)
+ *   beta  = beta_lo  + (beta_hi  - beta_lo)  (iy + 1/2) / ny   (towards the
+ *           spin axis)
+ * and is photon  first + iy * nx + ix.  Constraints: 0 <= a < 1,
+ * r_obs > r_bh = 1 + sqrt(1 - a^2), 0 <= incl <= pi, nx, ny >= 1, finite
+ * ranges. Cameras passed together must tile [0, n) in order with no gaps. */
+typedef struct {
+    double a, r_obs, incl;
+    int32_t nx, ny;
+    double alpha_lo, alpha_hi, beta_lo, beta_hi;
+    int64_t first;
+} gray_camera;
+
+/* Integrator parameters (Sec. 2 names them Delta, delta and epsilon). */
+typedef struct {
+    double step_frac;    /* Delta of the step-size rule eq. (2); ~1/32      > 0 */
+    double horizon_eps;  /* capture when r < r_bh (1 + horizon_eps)          > 0 */
+    double r_escape;     /* escape when r > r_escape and k^r > 0             > 0 */
+    double xi_eps;       /* epsilon of eq. (4); ~1e-3                        > 0 */
+    double euler_div;    /* Euler fallback step h / euler_div; 9 in Sec. 2  >= 1 */
+    double disk_rmin;    /* recorder window [rmin, rmax]; rmin < 0: r_ISCO(a)     */
+    double disk_rmax;
+    int32_t max_steps;   /* total accepted steps before GRAY_UNFINISHED     >= 1 */
+    int32_t call_steps;  /* > 0: advance each photon at most this many steps in
+                            this call and leave it GRAY_RUNNING (resumable);
+                            0: run to termination                                */
+    int32_t precision;   /* gray_precision                                       */
+    uint32_t flags;      /* GRAY_RECORD_DISK                                     */
+} gray_params;
+
+typedef struct {
+    void *x;
+    void *lo;
+    int32_t *status;
+    int32_t *steps;
+    int32_t *cam;
+    int32_t *counters;
+    double *mark;
+    double *disk;
+    int64_t n;
+    int64_t stride;
+} gray_state;
+
+/* Outputs of gray_classify, all device memory, all rows `stride` apart
+ * (the state's stride). */
+typedef struct {
+    int8_t *flag;     /* required [n]: gray_status of each photon              */
+    double *xf;       /* optional 8 rows: final state in double (FP32C: hi+lo) */
+    double *cons;     /* optional 9 rows: E0, L0, Q0 at the camera; E, L, Q at the
+                         final state; drifts dE = |E/E0 - 1|,
+                         dL = |L - L0| / (|L0| + E0),
+                         dQ = |Q - Q0| / (|Q0| + L0^2 + E0^2), evaluated at the
+                         final state, or for captured photons at `mark` when the
+                         state carries one                                     */
+    int32_t *counts;  /* optional [ncam][5]: photons per camera and status     */
+} gray_result;
+
+/* Bytes of device workspace that gray_integrate needs for n photons over ncam
+ * cameras (per-camera constants and the photon work queue). Returns 0 on
+ * invalid arguments. */
+size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params *p);
+
+/* Image plane -> initial state (Sec. 2 defers the set-up; see the camera
+ * comment). Writes x (and lo), status = GRAY_RUNNING, steps = 0, cam, and
+ * clears counters, mark and disk when present. */
+int gray_camera_init(const gray_camera *cams, int32_t ncam, const gray_params *p,
+                     gray_state *s, void *hip_stream);
+
+/* Integrate every GRAY_RUNNING photon with the scheme of Sec. 2 until it is
+ * captured, escapes, turns non-finite or reaches max_steps (or until it has
+ * taken call_steps steps in this call). Photons of all cameras share one
+ * persistent launch; a wave refills lanes whose photon finished from a global
+ * queue. Resumable: the state is the checkpoint, and repeated calls with
+ * call_steps > 0 reproduce a single call exactly (bit for bit in FP64).
+ * workspace: device memory of gray_workspace_size() bytes, 256-byte aligned. */
+int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p,
+                   gray_state *s, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Final classification and conservation diagnostics (E, L_z and Carter's Q,
+ * Sec. 1) of every photon; see gray_result. */
+int gray_classify(const gray_camera *cams, int32_t ncam, const gray_params *p,
+                  const gray_state *s, gray_result *out, void *hip_stream);
+
+/* Static description of an error code; for GRAY_EDEVICE, of the last device
+ * error seen by the calling thread. Never NULL. */
+const char *gray_strerror(int code);
+
+/* Library version as an integer MAJOR * 10000 + MINOR * 100 + PATCH. */
+int gray_version(void);
+
+/* sizeof of the ABI structs, for bindings to check their mirrors:
+ * which = 0 gray_camera, 1 gray_params, 2 gray_state, 3 gray_result;
+ * 0 for any other value. */
+size_t gray_struct_size(int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRAY_H */

@@ -1,0 +1,647 @@
+// gray.hip -- HIP kernels and C ABI (include/gray.h) of the MI355X Kerr
+// photon-geodesic integrator.
+//
+// Scheme (Chan, Psaltis & Ozel 2013, Sec. 2): classical RK4 on the 8-component
+// second-order geodesic equation, the step-size rule of eq. (2), the horizon
+// stop, the theta remap of eq. (3) and the null-condition monitor of eq. (4)
+// with a forward-Euler re-integration at h / 9.
+//
+// GPU design: one photon per lane of a 64-wide wavefront, state in VGPRs for
+// the whole trajectory, structure-of-arrays state in HBM read once and written
+// once per photon. The integrate kernel is persistent: a wave holds 64 photons,
+// and whenever enough lanes have finished it hands them the next photons of a
+// 64-photon chunk taken from one global counter (one atomic per 64 photons),
+// so lanes stay busy while step counts differ per photon.
+#include "../../include/gray.h"
+#include "kerr.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+namespace gray {
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_last_error[512] = "no device error";
+
+static int device_error(const char *what, hipError_t e)
+{
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return GRAY_EDEVICE;
+}
+
+static int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GRAY_OK : device_error(what, e);
+}
+
+// ------------------------------------------------------------ constants
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kCamChunk = 16;          // cameras per by-value kernel argument
+constexpr unsigned kQueueChunk = 64;   // photons per queue grab (one per lane)
+constexpr size_t kWsHeader = 256;      // queue counter, padded
+constexpr int64_t kMaxPhotons = (int64_t)1 << 31;
+
+// Per-camera constants the integrator needs, kept in the workspace.
+struct DevCam {
+    double a, a2, rbh, rcap, rmark, disk_rmin, disk_rmax, pad;
+};
+static_assert(sizeof(DevCam) == 64, "DevCam is one 64-byte record");
+
+// Camera geometry passed by value to the init and classify kernels.
+struct CamArg {
+    double a, r_obs, incl, alo, ahi, blo, bhi;
+    int64_t first;
+    int32_t nx, ny, index, pad;
+};
+struct CamChunk {
+    CamArg c[kCamChunk];
+    int32_t count;
+    int32_t pad;
+    int64_t lo, hi;   // photon range [lo, hi) covered by these cameras
+};
+struct SetupChunk {
+    DevCam c[kCamChunk];
+    int32_t base, count;
+};
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ unsigned lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ int find_camera(const CamChunk &ch, int64_t i)
+{
+    int k = 0;
+    for (int j = 1; j < ch.count; ++j)
+        if (i >= ch.c[j].first) k = j;
+    return k;
+}
+
+__device__ __forceinline__ void pixel_of(const CamArg &c, int64_t i, double &alpha, double &beta)
+{
+    const int64_t local = i - c.first;
+    const int32_t iy = (int32_t)(local / c.nx);
+    const int32_t ix = (int32_t)(local - (int64_t)iy * c.nx);
+    alpha = c.alo + (c.ahi - c.alo) * ((ix + 0.5) / c.nx);
+    beta = c.blo + (c.bhi - c.blo) * ((iy + 0.5) / c.ny);
+}
+
+// ------------------------------------------------------- camera initialisation
+struct InitArgs {
+    void *x, *lo;
+    int32_t *status, *steps, *cam, *counters;
+    double *mark, *disk;
+    int64_t stride;
+    int32_t precision, pad;
+    CamChunk ch;
+};
+
+__global__ __launch_bounds__(kBlock) void k_camera_init(InitArgs A)
+{
+    const int64_t i = A.ch.lo + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= A.ch.hi) return;
+    const CamArg &c = A.ch.c[find_camera(A.ch, i)];
+    double alpha, beta;
+    pixel_of(c, i, alpha, beta);
+    State<double> x;
+    camera_state(c.a, c.r_obs, c.incl, alpha, beta, x);
+    const int64_t S = A.stride;
+    if (A.precision == GRAY_FP64) {
+        double *X = (double *)A.x;
+        for (int k = 0; k < 8; ++k) X[k * S + i] = get(x, k);
+    } else {
+        float *H = (float *)A.x, *L = (float *)A.lo;
+        for (int k = 0; k < 8; ++k) {
+            const double v = get(x, k);
+            const float hi = (float)v;
+            H[k * S + i] = hi;
+            L[k * S + i] = (float)(v - (double)hi);
+        }
+    }
+    A.status[i] = GRAY_RUNNING;
+    A.steps[i] = 0;
+    A.cam[i] = c.index;
+    if (A.counters)
+        for (int k = 0; k < 3; ++k) A.counters[k * S + i] = 0;
+    if (A.mark) A.mark[1 * S + i] = 0.0;
+    if (A.disk)
+        for (int k = 0; k < 3; ++k) A.disk[k * S + i] = 0.0;
+}
+
+// ------------------------------------------------------------ workspace setup
+__global__ void k_setup(DevCam *table, unsigned *queue, SetupChunk ch)
+{
+    const int j = threadIdx.x;
+    if (j < ch.count) table[ch.base + j] = ch.c[j];
+    if (ch.base == 0 && j == 0) *queue = 0u;
+}
+
+__device__ __forceinline__ bool finite_state(const State<double> &x)
+{
+    return isfinite(x.t) && isfinite(x.r) && isfinite(x.th) && isfinite(x.ph) && isfinite(x.kt) &&
+           isfinite(x.kr) && isfinite(x.kth) && isfinite(x.kph);
+}
+
+// ------------------------------------------------------- persistent integrator
+struct IntArgs {
+    double *x;
+    int32_t *status, *steps;
+    const int32_t *cam;
+    int32_t *counters;
+    double *mark, *disk;
+    const DevCam *cams;
+    unsigned *queue;
+    int64_t n, stride;
+    double step_frac, xi_eps, euler_div, r_escape;
+    int32_t max_steps, call_steps;
+    uint32_t flags;
+    int32_t refill;
+};
+
+__global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
+{
+    const unsigned lane = threadIdx.x & (kWave - 1);
+    const int64_t S = A.stride;
+    const bool record_disk = (A.flags & GRAY_RECORD_DISK) != 0;
+
+    bool active = false;
+    int64_t id = 0;
+    State<double> x;
+    StepConst<double> K;
+    double rcap = 0.0, rmark = 0.0, dmin = 0.0, dmax = 0.0;
+    int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0;
+    bool hit = false;
+
+    unsigned chunk_next = 0, chunk_end = 0;
+    bool exhausted = false;
+
+    for (;;) {
+        const uint64_t idle = ballot(!active);
+        if (__popcll(idle) >= A.refill || idle == ~0ull) {
+            if (chunk_next >= chunk_end && !exhausted) {
+                unsigned base = 0;
+                if (lane == 0) base = atomicAdd(A.queue, kQueueChunk);
+                base = __builtin_amdgcn_readfirstlane(base);
+                if ((int64_t)base + kQueueChunk >= A.n) exhausted = true;
+                chunk_next = (int64_t)base < A.n ? base : (unsigned)A.n;
+                chunk_end = (int64_t)base + kQueueChunk < A.n ? base + kQueueChunk : (unsigned)A.n;
+            }
+            const unsigned avail = chunk_end - chunk_next;
+            if (avail > 0) {
+                const unsigned rank = lane_rank(idle);
+                if (!active && rank < avail) {
+                    id = (int64_t)(chunk_next + rank);
+                    const int32_t st = A.status[id];
+                    if (st == GRAY_RUNNING) {
+                        x.t = A.x[0 * S + id];
+                        x.r = A.x[1 * S + id];
+                        x.th = A.x[2 * S + id];
+                        x.ph = A.x[3 * S + id];
+                        x.kt = A.x[4 * S + id];
+                        x.kr = A.x[5 * S + id];
+                        x.kth = A.x[6 * S + id];
+                        x.kph = A.x[7 * S + id];
+                        const DevCam cm = A.cams[A.cam[id]];
+                        K.a = cm.a;
+                        K.a2 = cm.a2;
+                        K.rbh = cm.rbh;
+                        K.step_frac = A.step_frac;
+                        K.xi_eps = A.xi_eps;
+                        K.euler_div = A.euler_div;
+                        rcap = cm.rcap;
+                        rmark = cm.rmark;
+                        dmin = cm.disk_rmin;
+                        dmax = cm.disk_rmax;
+                        nsteps = A.steps[id];
+                        ncall = 0;
+                        ne = A.counters ? A.counters[0 * S + id] : 0;
+                        nr = A.counters ? A.counters[1 * S + id] : 0;
+                        hit = record_disk && A.disk[0 * S + id] != 0.0;
+                        active = true;
+                    }
+                }
+                const unsigned taken = __popcll(idle) < avail ? (unsigned)__popcll(idle) : avail;
+                chunk_next += taken;
+            }
+            if (exhausted && chunk_next >= chunk_end && ballot(active) == 0ull) break;
+        }
+
+        if (active) {
+            const State<double> xp = x;
+            const int fl = rk4_step(K, x);
+            int32_t st = GRAY_RUNNING;
+            if (fl < 0) {
+                st = GRAY_NONFINITE;
+            } else {
+                ++nsteps;
+                ++ncall;
+                ne += fl & 1;
+                nr += (fl >> 1) & 1;
+                if (record_disk && !hit &&
+                    (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0) {
+                    const double f = (kHalfPi - xp.th) / (x.th - xp.th);
+                    const double rc = xp.r + f * (x.r - xp.r);
+                    if (rc >= dmin && rc <= dmax) {
+                        double E, L, Q;
+                        conserved(K.a, x, E, L, Q);
+                        A.disk[0 * S + id] = rc;
+                        A.disk[1 * S + id] = xp.ph + f * (x.ph - xp.ph);
+                        A.disk[2 * S + id] = disk_redshift(K.a, rc, E, L);
+                        hit = true;
+                    }
+                }
+                if (A.mark && xp.r >= rmark && x.r < rmark) {
+                    A.mark[0 * S + id] = xp.t;
+                    A.mark[1 * S + id] = xp.r;
+                    A.mark[2 * S + id] = xp.th;
+                    A.mark[3 * S + id] = xp.ph;
+                    A.mark[4 * S + id] = xp.kt;
+                    A.mark[5 * S + id] = xp.kr;
+                    A.mark[6 * S + id] = xp.kth;
+                    A.mark[7 * S + id] = xp.kph;
+                }
+                if (!finite_state(x)) st = GRAY_NONFINITE;
+                else if (x.r < rcap) st = GRAY_CAPTURED;
+                else if (x.r > A.r_escape && x.kr > 0.0) st = GRAY_ESCAPED;
+                else if (nsteps >= A.max_steps) st = GRAY_UNFINISHED;
+            }
+            if (st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps)) {
+                A.x[0 * S + id] = x.t;
+                A.x[1 * S + id] = x.r;
+                A.x[2 * S + id] = x.th;
+                A.x[3 * S + id] = x.ph;
+                A.x[4 * S + id] = x.kt;
+                A.x[5 * S + id] = x.kr;
+                A.x[6 * S + id] = x.kth;
+                A.x[7 * S + id] = x.kph;
+                A.status[id] = st;
+                A.steps[id] = nsteps;
+                if (A.counters) {
+                    A.counters[0 * S + id] = ne;
+                    A.counters[1 * S + id] = nr;
+                }
+                active = false;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- classification
+struct ClassArgs {
+    const void *x, *lo;
+    const int32_t *status;
+    const double *mark;
+    int8_t *flag;
+    double *xf, *cons;
+    int32_t *counts;
+    int64_t stride;
+    int32_t precision, pad;
+    CamChunk ch;
+};
+
+__global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_classify(ClassArgs A)
+{
+    const int64_t i = A.ch.lo + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= A.ch.hi) return;
+    const int k = find_camera(A.ch, i);
+    const CamArg &c = A.ch.c[k];
+    const int64_t S = A.stride;
+    const int32_t st = A.status[i];
+    A.flag[i] = (int8_t)st;
+    if (A.counts) atomicAdd(&A.counts[c.index * 5 + (st >= 0 && st < 5 ? st : 4)], 1);
+
+    State<double> xf;
+    double v[8];
+    if (A.precision == GRAY_FP64) {
+        const double *X = (const double *)A.x;
+        for (int j = 0; j < 8; ++j) v[j] = X[j * S + i];
+    } else {
+        const float *H = (const float *)A.x, *L = (const float *)A.lo;
+        for (int j = 0; j < 8; ++j) v[j] = (double)H[j * S + i] + (double)L[j * S + i];
+    }
+    xf.t = v[0]; xf.r = v[1]; xf.th = v[2]; xf.ph = v[3];
+    xf.kt = v[4]; xf.kr = v[5]; xf.kth = v[6]; xf.kph = v[7];
+    if (A.xf)
+        for (int j = 0; j < 8; ++j) A.xf[j * S + i] = v[j];
+    if (A.cons) {
+        double alpha, beta;
+        pixel_of(c, i, alpha, beta);
+        State<double> x0;
+        camera_state(c.a, c.r_obs, c.incl, alpha, beta, x0);
+        double E0, L0, Q0, E, L, Q;
+        conserved(c.a, x0, E0, L0, Q0);
+        conserved(c.a, xf, E, L, Q);
+        State<double> xd = xf;
+        if (st == GRAY_CAPTURED && A.mark && A.mark[1 * S + i] > 0.0) {
+            xd.t = A.mark[0 * S + i]; xd.r = A.mark[1 * S + i];
+            xd.th = A.mark[2 * S + i]; xd.ph = A.mark[3 * S + i];
+            xd.kt = A.mark[4 * S + i]; xd.kr = A.mark[5 * S + i];
+            xd.kth = A.mark[6 * S + i]; xd.kph = A.mark[7 * S + i];
+        }
+        double Ed, Ld, Qd;
+        conserved(c.a, xd, Ed, Ld, Qd);
+        double *C = A.cons;
+        C[0 * S + i] = E0;
+        C[1 * S + i] = L0;
+        C[2 * S + i] = Q0;
+        C[3 * S + i] = E;
+        C[4 * S + i] = L;
+        C[5 * S + i] = Q;
+        C[6 * S + i] = fabs(Ed / E0 - 1.0);
+        C[7 * S + i] = fabs(Ld - L0) / (fabs(L0) + fabs(E0));
+        C[8 * S + i] = fabs(Qd - Q0) / (fabs(Q0) + L0 * L0 + E0 * E0);
+    }
+}
+
+// ------------------------------------------------------------- host helpers
+static int validate_params(const gray_params *p)
+{
+    if (!p) return GRAY_EINVAL;
+    if (!(p->step_frac > 0.0 && std::isfinite(p->step_frac))) return GRAY_EINVAL;
+    if (!(p->horizon_eps > 0.0 && std::isfinite(p->horizon_eps))) return GRAY_EINVAL;
+    if (!(p->r_escape > 0.0 && std::isfinite(p->r_escape))) return GRAY_EINVAL;
+    if (!(p->xi_eps > 0.0)) return GRAY_EINVAL;
+    if (!(p->euler_div >= 1.0 && std::isfinite(p->euler_div))) return GRAY_EINVAL;
+    if (p->max_steps < 1 || p->call_steps < 0) return GRAY_EINVAL;
+    if (p->precision != GRAY_FP64 && p->precision != GRAY_FP32C) return GRAY_EINVAL;
+    if (p->flags & ~GRAY_RECORD_DISK) return GRAY_EINVAL;
+    if (p->flags & GRAY_RECORD_DISK) {
+        if (!(p->disk_rmax > 0.0) || std::isnan(p->disk_rmin)) return GRAY_EINVAL;
+    }
+    return GRAY_OK;
+}
+
+static int validate_cameras(const gray_camera *cams, int32_t ncam, int64_t n)
+{
+    if (!cams || ncam < 1) return GRAY_EINVAL;
+    int64_t next = 0;
+    for (int32_t k = 0; k < ncam; ++k) {
+        const gray_camera &c = cams[k];
+        if (!(c.a >= 0.0 && c.a < 1.0)) return GRAY_EINVAL;
+        if (!(c.r_obs > horizon_radius(c.a) && std::isfinite(c.r_obs))) return GRAY_EINVAL;
+        if (!(c.incl >= 0.0 && c.incl <= kPi)) return GRAY_EINVAL;
+        if (c.nx < 1 || c.ny < 1) return GRAY_EINVAL;
+        if (!(std::isfinite(c.alpha_lo) && std::isfinite(c.alpha_hi) && std::isfinite(c.beta_lo) &&
+              std::isfinite(c.beta_hi)))
+            return GRAY_EINVAL;
+        if (c.first != next) return GRAY_EINVAL;
+        next += (int64_t)c.nx * c.ny;
+        if (next > n) return GRAY_EINVAL;
+    }
+    return next == n ? GRAY_OK : GRAY_EINVAL;
+}
+
+static int validate_state(const gray_state *s, const gray_params *p)
+{
+    if (!s) return GRAY_EINVAL;
+    if (s->n < 0 || s->n >= kMaxPhotons - (int64_t)kQueueChunk) return GRAY_EINVAL;
+    if (s->n == 0) return GRAY_OK;
+    if (s->stride < s->n || s->stride % kWave != 0) return GRAY_EINVAL;
+    if (!s->x || !s->status || !s->steps || !s->cam) return GRAY_EINVAL;
+    if (p->precision == GRAY_FP32C && !s->lo) return GRAY_EINVAL;
+    if (p->precision == GRAY_FP64 && s->lo) return GRAY_EINVAL;
+    if ((p->flags & GRAY_RECORD_DISK) && !s->disk) return GRAY_EINVAL;
+    return GRAY_OK;
+}
+
+static void fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, CamChunk &ch)
+{
+    memset(&ch, 0, sizeof ch);
+    ch.count = cnt;
+    for (int32_t j = 0; j < cnt; ++j) {
+        const gray_camera &c = cams[k0 + j];
+        CamArg &o = ch.c[j];
+        o.a = c.a;
+        o.r_obs = c.r_obs;
+        o.incl = c.incl;
+        o.alo = c.alpha_lo;
+        o.ahi = c.alpha_hi;
+        o.blo = c.beta_lo;
+        o.bhi = c.beta_hi;
+        o.first = c.first;
+        o.nx = c.nx;
+        o.ny = c.ny;
+        o.index = k0 + j;
+    }
+    ch.lo = cams[k0].first;
+    const gray_camera &last = cams[k0 + cnt - 1];
+    ch.hi = last.first + (int64_t)last.nx * last.ny;
+}
+
+struct DeviceInfo {
+    int cus = 0;
+    int blocks_per_cu_fp64 = 0;
+};
+static std::mutex g_dev_mutex;
+static DeviceInfo g_dev[64];
+
+static int device_info(DeviceInfo &out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error("hipGetDevice", e);
+    if (dev < 0 || dev >= 64) return device_error("device index", hipErrorInvalidDevice);
+    std::lock_guard<std::mutex> lk(g_dev_mutex);
+    DeviceInfo &d = g_dev[dev];
+    if (d.cus == 0) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate_fp64, kBlock, 0);
+        if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+        d.blocks_per_cu_fp64 = nb > 0 ? nb : 1;
+        d.cus = cus;
+    }
+    out = d;
+    return GRAY_OK;
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+} // namespace gray
+
+using namespace gray;
+
+extern "C" size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params *p)
+{
+    if (n < 0 || ncam < 1 || validate_params(p) != GRAY_OK) return 0;
+    return kWsHeader + (size_t)ncam * sizeof(DevCam);
+}
+
+extern "C" int gray_camera_init(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
+                                void *hip_stream)
+{
+    int e = validate_params(p);
+    if (e) return e;
+    if ((e = validate_state(s, p))) return e;
+    if (s->n == 0) return GRAY_OK;
+    if ((e = validate_cameras(cams, ncam, s->n))) return e;
+    if (p->precision != GRAY_FP64) return GRAY_EUNSUPPORTED;
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
+        InitArgs A;
+        memset(&A, 0, sizeof A);
+        A.x = s->x;
+        A.lo = s->lo;
+        A.status = s->status;
+        A.steps = s->steps;
+        A.cam = s->cam;
+        A.counters = s->counters;
+        A.mark = s->mark;
+        A.disk = s->disk;
+        A.stride = s->stride;
+        A.precision = p->precision;
+        fill_chunk(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk, A.ch);
+        const int64_t cnt = A.ch.hi - A.ch.lo;
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL(k_camera_init, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, A);
+        if ((e = check_launch("camera_init launch"))) return e;
+    }
+    return GRAY_OK;
+}
+
+extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
+                              void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    int e = validate_params(p);
+    if (e) return e;
+    if ((e = validate_state(s, p))) return e;
+    if (s->n == 0) return GRAY_OK;
+    if ((e = validate_cameras(cams, ncam, s->n))) return e;
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0 ||
+        workspace_bytes < gray_workspace_size(s->n, ncam, p))
+        return GRAY_EWORKSPACE;
+    if (p->precision != GRAY_FP64) return GRAY_EUNSUPPORTED;
+
+    DeviceInfo dev;
+    if ((e = device_info(dev))) return e;
+    hipStream_t st = (hipStream_t)hip_stream;
+    unsigned *queue = (unsigned *)workspace;
+    DevCam *table = (DevCam *)((char *)workspace + kWsHeader);
+
+    for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
+        SetupChunk ch;
+        memset(&ch, 0, sizeof ch);
+        ch.base = k0;
+        ch.count = ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk;
+        for (int j = 0; j < ch.count; ++j) {
+            const gray_camera &c = cams[k0 + j];
+            DevCam &d = ch.c[j];
+            d.a = c.a;
+            d.a2 = c.a * c.a;
+            d.rbh = horizon_radius(c.a);
+            d.rcap = d.rbh * (1.0 + p->horizon_eps);
+            d.rmark = 2.0 * d.rbh;
+            d.disk_rmin = p->disk_rmin < 0.0 ? isco_radius(c.a) : p->disk_rmin;
+            d.disk_rmax = p->disk_rmax;
+        }
+        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, queue, ch);
+        if ((e = check_launch("setup launch"))) return e;
+    }
+
+    IntArgs A;
+    memset(&A, 0, sizeof A);
+    A.x = (double *)s->x;
+    A.status = s->status;
+    A.steps = s->steps;
+    A.cam = s->cam;
+    A.counters = s->counters;
+    A.mark = s->mark;
+    A.disk = s->disk;
+    A.cams = table;
+    A.queue = queue;
+    A.n = s->n;
+    A.stride = s->stride;
+    A.step_frac = p->step_frac;
+    A.xi_eps = p->xi_eps;
+    A.euler_div = p->euler_div;
+    A.r_escape = p->r_escape;
+    A.max_steps = p->max_steps;
+    A.call_steps = p->call_steps;
+    A.flags = p->flags;
+    A.refill = 1;
+    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu_fp64;
+    const int64_t need = blocks_for(s->n);
+    const unsigned grid = (unsigned)(need < resident ? need : resident);
+    hipLaunchKernelGGL(k_integrate_fp64, dim3(grid), dim3(kBlock), 0, st, A);
+    return check_launch("integrate launch");
+}
+
+extern "C" int gray_classify(const gray_camera *cams, int32_t ncam, const gray_params *p, const gray_state *s,
+                             gray_result *out, void *hip_stream)
+{
+    int e = validate_params(p);
+    if (e) return e;
+    if ((e = validate_state(s, p))) return e;
+    if (!out) return GRAY_EINVAL;
+    if (s->n == 0) return GRAY_OK;
+    if ((e = validate_cameras(cams, ncam, s->n))) return e;
+    if (!out->flag) return GRAY_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (out->counts) {
+        const int64_t m = (int64_t)ncam * 5;
+        hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(m)), dim3(kBlock), 0, st, out->counts, m);
+        if ((e = check_launch("classify zero launch"))) return e;
+    }
+    for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
+        ClassArgs A;
+        memset(&A, 0, sizeof A);
+        A.x = s->x;
+        A.lo = s->lo;
+        A.status = s->status;
+        A.mark = s->mark;
+        A.flag = out->flag;
+        A.xf = out->xf;
+        A.cons = out->cons;
+        A.counts = out->counts;
+        A.stride = s->stride;
+        A.precision = p->precision;
+        fill_chunk(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk, A.ch);
+        const int64_t cnt = A.ch.hi - A.ch.lo;
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL(k_classify, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, A);
+        if ((e = check_launch("classify launch"))) return e;
+    }
+    return GRAY_OK;
+}
+
+extern "C" const char *gray_strerror(int code)
+{
+    switch (code) {
+    case GRAY_OK: return "success";
+    case GRAY_EINVAL: return "invalid argument";
+    case GRAY_EDEVICE: return g_last_error;
+    case GRAY_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case GRAY_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown error code";
+    }
+}
+
+extern "C" int gray_version(void) { return 100; }
+
+extern "C" size_t gray_struct_size(int which)
+{
+    switch (which) {
+    case 0: return sizeof(gray_camera);
+    case 1: return sizeof(gray_params);
+    case 2: return sizeof(gray_state);
+    case 3: return sizeof(gray_result);
+    default: return 0;
+    }
+}

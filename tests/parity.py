@@ -1,0 +1,138 @@
+"""GPU-vs-oracle comparison helpers for the `gpu` tests.
+
+The GPU side runs through the C ABI (paper_1303_5057_amd.gray); the oracle
+side builds its own initial states from the same camera descriptors and
+integrates them on the host. Nothing flows from the GPU into the oracle.
+
+Parity rules (numbers from the workload specification):
+  * capture / escape flags are bit-exact for rays farther than 1e-3 M from
+    the critical curve, measured on the ray's own constants of motion
+    (oracle side);
+  * final states of rays whose step counts agree match to a relative
+    tolerance (1e-5 for FP64) per component, with per-component floors that
+    keep near-zero components meaningful: 1 for t, r, theta, phi, k^t, k^r
+    and 1/r for the angular rates k^theta and k^phi;
+  * Euler-fallback and remap counters agree exactly where step counts agree;
+  * the fraction of rays (outside the band) whose step counts differ is
+    reported and must stay below 1e-3.
+"""
+from __future__ import annotations
+
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+import analytic
+import oracle
+from paper_1303_5057_amd import gray as G
+from paper_1303_5057_amd import workloads as W
+
+BAND = 1e-3
+NTHREADS = int(os.environ.get("ORACLE_THREADS", "0"))
+
+
+def oracle_params(p: W.Params):
+    return oracle.make_params(step_frac=p.step_frac, horizon_eps=p.horizon_eps, r_escape=p.r_escape,
+                              xi_eps=p.xi_eps, euler_div=p.euler_div, max_steps=p.max_steps,
+                              record_disk=p.record_disk, disk_rmin=p.disk_rmin,
+                              disk_rmax=p.disk_rmax)
+
+
+def pixel_ab(cam: W.Camera, ids):
+    ids = np.asarray(ids)
+    iy, ix = ids // cam.nx, ids % cam.nx
+    al = cam.alpha_lo + (cam.alpha_hi - cam.alpha_lo) * ((ix + 0.5) / cam.nx)
+    be = cam.beta_lo + (cam.beta_hi - cam.beta_lo) * ((iy + 0.5) / cam.ny)
+    return al, be
+
+
+@dataclass
+class OracleRun:
+    status: np.ndarray
+    steps: np.ndarray
+    x: np.ndarray         # (n, 8)
+    n_euler: np.ndarray
+    n_remap: np.ndarray
+    disk: np.ndarray | None
+    band_dist: np.ndarray
+    cons0: np.ndarray     # (n, 3)
+
+
+def run_oracle(cam: W.Camera, p: W.Params, ids=None) -> OracleRun:
+    if ids is None:
+        ids = np.arange(cam.n)
+    al, be = pixel_ab(cam, ids)
+    X0 = np.array([oracle.camera(cam.a, cam.r_obs, cam.incl, x, y) for x, y in zip(al, be)])
+    res = oracle.run(oracle_params(p), cam.a, X0, nthreads=NTHREADS, want_disk=p.record_disk)
+    cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
+    band = analytic.CriticalBand(cam.a, cam.incl)
+    d = band.distance(cons0[:, 0], cons0[:, 1], cons0[:, 2])
+    return OracleRun(res.status, res.steps, res.x, res.n_euler, res.n_remap, res.disk, d, cons0)
+
+
+@dataclass
+class GpuRun:
+    status: np.ndarray
+    steps: np.ndarray
+    x: np.ndarray        # (8, n) final state in double
+    counters: np.ndarray  # (3, n)
+    flag: np.ndarray
+    cons: np.ndarray     # (9, n)
+    counts: np.ndarray   # (ncam, 5)
+    disk: np.ndarray | None
+    offsets: np.ndarray
+
+
+def run_gpu(cams, p: W.Params, call_steps: int = 0, batch: "G.Batch" = None,
+            init: bool = True) -> GpuRun:
+    import torch
+    b = batch or G.Batch(cams, p)
+    if init:
+        b.camera_init()
+    if call_steps > 0:
+        b.set_call_steps(call_steps)
+        for _ in range(1 + p.max_steps // call_steps):
+            b.integrate()
+        b.set_call_steps(0)
+    else:
+        b.integrate()
+    res = b.classify()
+    torch.cuda.synchronize()
+    offs = np.cumsum([0] + [c.n for c in b.cams])
+    return GpuRun(b.rows(b.status, 1)[0], b.rows(b.steps, 1)[0], b.rows(res.xf, 8),
+                  b.rows(b.counters, 3), b.rows(res.flag, 1)[0], b.rows(res.cons, 9),
+                  res.counts.view(-1, 5).cpu().numpy(),
+                  b.rows(b.disk, 3) if b.disk is not None else None, offs)
+
+
+def state_close(xg: np.ndarray, xo: np.ndarray, rtol: float) -> np.ndarray:
+    """Per-ray boolean: every component within rtol (|xo| + floor)."""
+    r = np.abs(xo[:, 1])
+    floor = np.stack([np.ones_like(r)] * 6 + [1.0 / r, 1.0 / r], axis=1)
+    err = np.abs(xg - xo) / (np.abs(xo) + floor)
+    return np.all(err <= rtol, axis=1), err
+
+
+@dataclass
+class Report:
+    n: int
+    outside_band: int
+    flag_mismatch: int
+    step_mismatch: int
+    state_bad: int
+    counter_bad: int
+    max_err: float
+
+
+def compare(g_status, g_steps, g_x, g_counters, ora: OracleRun, rtol: float) -> Report:
+    """g_* are GPU values for the same rays as `ora` (g_x shape (n, 8))."""
+    far = ora.band_dist > BAND
+    flag_mis = int(np.sum((g_status != ora.status) & far))
+    same = (g_steps == ora.steps) & (g_status == ora.status)
+    ok, err = state_close(g_x, ora.x, rtol)
+    state_bad = int(np.sum(same & ~ok))
+    cnt_bad = int(np.sum(same & ((g_counters[0] != ora.n_euler) | (g_counters[1] != ora.n_remap))))
+    return Report(n=len(g_status), outside_band=int(far.sum()), flag_mismatch=flag_mis,
+                  step_mismatch=int(np.sum(~same & far)), state_bad=state_bad, counter_bad=cnt_bad,
+                  max_err=float(err[same].max()) if same.any() else 0.0)

@@ -1,0 +1,157 @@
+"""GPU parity: libgray (through its C ABI) against the FP64 CPU oracle.
+
+Workloads are the seeded synthetic image-plane grids of the workload
+specification at sizes the oracle finishes in seconds, plus the full-size
+edge-on Kerr grid with the oracle on a deterministic sample of its rays.
+See tests/parity.py for the comparison rules.
+"""
+import numpy as np
+import pytest
+
+import analytic
+import oracle
+from parity import compare, run_gpu, run_oracle
+from paper_1303_5057_amd import gray as G
+from paper_1303_5057_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-5
+
+
+def _check(rep, allow_step_mismatch=1e-3):
+    print(rep, flush=True)
+    assert rep.flag_mismatch == 0
+    assert rep.state_bad == 0
+    assert rep.counter_bad == 0
+    assert rep.step_mismatch <= allow_step_mismatch * rep.n
+
+
+def test_c1_schwarzschild_full_grid_fp64():
+    cam, p = W.C1, W.Params()
+    g = run_gpu([cam], p)
+    o = run_oracle(cam, p)
+    _check(compare(g.status, g.steps, g.x.T, g.counters, o, RTOL64))
+    assert np.array_equal(g.flag, g.status)
+    # independent of the oracle: the sqrt(27) shadow on the pixel grid
+    al, be = np.meshgrid(-10 + 20 * (np.arange(64) + 0.5) / 64, -10 + 20 * (np.arange(64) + 0.5) / 64)
+    captured = (np.hypot(al, be) < analytic.SQRT27).ravel()
+    assert np.array_equal(g.status == G.CAPTURED, captured)
+    assert g.counts.tolist() == [np.bincount(g.status, minlength=5).tolist()]
+
+
+def test_c2_kerr_ragged_grid_fp64():
+    """a = 0.99 edge-on window at 97 x 95: many 64-photon chunks plus a ragged tail."""
+    cam, p = W.scaled(W.C2, 97, 95), W.Params()
+    g = run_gpu([cam], p)
+    o = run_oracle(cam, p)
+    _check(compare(g.status, g.steps, g.x.T, g.counters, o, RTOL64))
+    assert set(np.unique(g.status)) == {G.CAPTURED, G.ESCAPED}
+
+
+def test_c2_full_size_sampled_fp64():
+    """Full 512 x 512 launch (as timed by the benchmark); the oracle traces every
+    8th row and column."""
+    cam, p = W.C2, W.Params()
+    g = run_gpu([cam], p)
+    ids = W.subsample_ids(cam, 8)
+    o = run_oracle(cam, p, ids)
+    _check(compare(g.status[ids], g.steps[ids], g.x.T[ids], g.counters[:, ids], o, RTOL64))
+    assert np.all((g.status == G.CAPTURED) | (g.status == G.ESCAPED))
+
+
+def test_many_cameras_one_launch_fp64():
+    """Seeded sweep cameras (spin, inclination, size) packed into one launch;
+    each camera's slice matches the oracle run of that camera alone."""
+    cams = W.sweep_cameras(count=7, side_lo=9, side_hi=40)
+    p = W.Params()
+    g = run_gpu(cams, p)
+    for k, cam in enumerate(cams):
+        sl = slice(g.offsets[k], g.offsets[k + 1])
+        o = run_oracle(cam, p)
+        _check(compare(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, RTOL64))
+        assert g.counts[k].tolist() == np.bincount(g.status[sl], minlength=5).tolist()
+
+
+def test_resume_is_bitwise_fp64():
+    """Repeated calls of call_steps steps reproduce a single call exactly."""
+    cam, p = W.scaled(W.C2, 40, 37), W.Params()
+    one = run_gpu([cam], p)
+    many = run_gpu([cam], p, call_steps=37)
+    assert np.array_equal(one.status, many.status)
+    assert np.array_equal(one.steps, many.steps)
+    assert np.array_equal(one.counters, many.counters)
+    assert np.array_equal(one.x, many.x)
+
+
+def test_unfinished_and_nonfinite_fp64():
+    import torch
+    cam = W.scaled(W.C2, 16)
+    p = W.Params(max_steps=50)
+    g = run_gpu([cam], p)
+    assert np.all(g.status == G.UNFINISHED) and np.all(g.steps == 50)
+    b = G.Batch([cam], W.Params())
+    b.camera_init()
+    x = b.x.view(8, b.stride)
+    x[1, 3] = float("nan")
+    x[5, 100] = float("inf")
+    x[6, 200] = float("nan")
+    g = run_gpu([cam], W.Params(), batch=b, init=False)
+    bad = [3, 100, 200]
+    assert np.all(g.status[bad] == G.NONFINITE)
+    ok = np.setdiff1d(np.arange(cam.n), bad)
+    assert np.all((g.status[ok] == G.CAPTURED) | (g.status[ok] == G.ESCAPED))
+    torch.cuda.synchronize()
+
+
+def test_pole_case_and_axis_ray_fp64():
+    p = W.Params()
+    cams = [W.pole_camera(np.radians(d)) for d in (0.0, 123.0)]
+    cams.append(W.Camera(0.5, 1000.0, 0.0, 1, 1, 0.0, 0.0, 0.0, 0.0))   # exactly on the axis
+    g = run_gpu(cams, p)
+    for k in range(2):
+        o = run_oracle(cams[k], p)
+        assert g.status[k] == G.CAPTURED and g.counters[1, k] >= 2
+        assert g.steps[k] == o.steps[0] and g.counters[0, k] == o.n_euler[0]
+    assert g.status[2] == G.NONFINITE and g.steps[2] == 1
+
+
+def test_single_photon_and_odd_shapes_fp64():
+    p = W.Params()
+    cams = [W.scaled(W.C1, 1, 1), W.scaled(W.C2, 3, 1), W.scaled(W.C2, 1, 5), W.scaled(W.C1, 65, 1)]
+    g = run_gpu(cams, p)
+    for k, cam in enumerate(cams):
+        sl = slice(g.offsets[k], g.offsets[k + 1])
+        o = run_oracle(cam, p)
+        _check(compare(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, RTOL64), 0)
+
+
+def test_classify_conserved_quantities_fp64():
+    cam, p = W.scaled(W.C2, 48), W.Params()
+    g = run_gpu([cam], p)
+    o = run_oracle(cam, p)
+    c = g.cons
+    assert np.allclose(c[0:3].T, o.cons0, rtol=1e-12, atol=1e-12)
+    same = g.steps == o.steps
+    cf = np.array([oracle.conserved(cam.a, x) for x in o.x])
+    assert np.allclose(c[3:6].T[same], cf[same], rtol=1e-6, atol=1e-9)
+    esc = (g.status == G.ESCAPED) & (o.band_dist > 1e-3)
+    assert np.max(c[6:9, esc]) <= 1e-5
+    cap = g.status == G.CAPTURED
+    assert np.max(c[6:9, cap]) <= 1e-5     # measured at the last state with r >= 2 r_bh
+
+
+def test_disk_recorder_fp64():
+    """Equatorial-crossing recorder on the a = 0.9375, i = 17 deg window."""
+    cam = W.scaled(W.C3, 48)
+    p = W.Params(record_disk=True, disk_rmin=-1.0, disk_rmax=50.0)
+    g = run_gpu([cam], p)
+    o = run_oracle(cam, p)
+    same = (g.steps == o.steps) & (g.status == o.status)
+    assert same.mean() > 0.999
+    hit_g, hit_o = g.disk[0] > 0, o.disk[:, 0] > 0
+    assert np.array_equal(hit_g[same], hit_o[same])
+    assert hit_g.sum() > 0.3 * cam.n
+    m = same & hit_o
+    assert np.allclose(g.disk.T[m], o.disk[m], rtol=1e-9, atol=1e-9)
+    assert np.all(g.disk[0, hit_g] >= oracle.r_isco(cam.a)) and np.all(g.disk[0, hit_g] <= 50.0)
