@@ -2,10 +2,12 @@
 // integrator by instantiating the very same templated step (kerr.hpp) with a
 // counting number type on the host.
 //
-// Weights: add, sub, mul = 1 flop; fma = 2; div, sqrt = 1; sin and cos = 1
-// each. Comparisons, fabs and negation are free. The count is for the common
-// path of a step (no Euler fallback, no remap); it is the algorithmic work
-// per accepted photon-step used for the roofline.
+// Weights: add, sub, mul = 1 flop; fma = 2; a division or reciprocal = 1;
+// sqrt = 1; sin and cos of an angle = 1 each, however they are evaluated (the
+// kernel's polynomial and angle-addition evaluations are counted as the two
+// functions they stand for). Comparisons, fabs and negation are free. The
+// count is for the common path of a step (no Euler fallback, no remap); it is
+// the algorithmic work per accepted photon-step used for the roofline.
 //
 // Build and run (host only):
 //   hipcc -x hip --offload-host-only -O1 -I include flopcount.cpp -o flopcount && ./flopcount
@@ -33,12 +35,15 @@ inline bool operator!=(Flop a, Flop b) { return a.v != b.v; }
 inline Flop fabs(Flop a) { return Flop(std::fabs(a.v)); }
 inline Flop fma(Flop a, Flop b, Flop c) { ++g.fma; return Flop(a.v * b.v + c.v); }
 inline Flop sqrt(Flop a) { ++g.sqrt; return Flop(std::sqrt(a.v)); }
+inline Flop rcp(Flop a) { ++g.div; return Flop(1.0 / a.v); }
+inline Flop quot(Flop a, Flop b) { ++g.div; return Flop(a.v / b.v); }
 inline void sin_cos(Flop x, Flop &s, Flop &c)
 {
     g.trans += 2;
     s = Flop(std::sin(x.v));
     c = Flop(std::cos(x.v));
 }
+inline void shift_sincos(Flop, Flop, Flop, Flop th, Flop &s, Flop &c) { sin_cos(th, s, c); }
 
 #include "kerr.hpp"
 
@@ -49,7 +54,7 @@ int main()
     // all momentum components nonzero, far from the horizon, poles and the
     // static limit.
     StepConst<Flop> K;
-    K.a = 0.9; K.a2 = 0.81; K.rbh = horizon_radius(0.9);
+    K.B = make_spin(Flop(0.9)); K.rbh = horizon_radius(0.9);
     K.step_frac = 1.0 / 32; K.xi_eps = 1e-3; K.euler_div = 9.0;
     State<double> x0;
     camera_state(0.9, 12.0, 1.0, 4.0, 3.0, x0);
@@ -58,13 +63,14 @@ int main()
     x.kt = x0.kt; x.kr = x0.kr; x.kth = x0.kth; x.kph = x0.kph;
 
     g = Cnt();
-    const int fl = rk4_step(K, x);
+    Flop sn(std::sin(x0.th)), cn(std::cos(x0.th));
+    const int fl = rk4_step(K, x, sn, cn);
     const long step_flops = g.add + g.mul + 2 * g.fma + g.div + g.sqrt + g.trans;
     Cnt st = g;
 
     g = Cnt();
     Flop dkt, dkr, dkth, dkph;
-    accel<Flop>(K.a, K.a2, Flop(12.0), Flop(0.8), Flop(0.6), Flop(-1.0), Flop(-0.9), Flop(0.01),
+    accel<Flop>(K.B, Flop(12.0), Flop(0.8), Flop(0.6), Flop(-1.0), Flop(-0.9), Flop(0.01),
                 Flop(0.02), dkt, dkr, dkth, dkph);
     const long rhs_flops = g.add + g.mul + 2 * g.fma + g.div + g.sqrt + g.trans;
 

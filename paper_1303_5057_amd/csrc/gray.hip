@@ -178,6 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
     State<double> x;
     StepConst<double> K;
     double rcap = 0.0, rmark = 0.0, dmin = 0.0, dmax = 0.0;
+    double sth = 0.0, cth = 1.0;
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0;
     bool hit = false;
 
@@ -211,8 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                         x.kth = A.x[6 * S + id];
                         x.kph = A.x[7 * S + id];
                         const DevCam cm = A.cams[A.cam[id]];
-                        K.a = cm.a;
-                        K.a2 = cm.a2;
+                        K.B = make_spin(cm.a);
                         K.rbh = cm.rbh;
                         K.step_frac = A.step_frac;
                         K.xi_eps = A.xi_eps;
@@ -226,6 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                         ne = A.counters ? A.counters[0 * S + id] : 0;
                         nr = A.counters ? A.counters[1 * S + id] : 0;
                         hit = record_disk && A.disk[0 * S + id] != 0.0;
+                        sin_cos(x.th, sth, cth);
                         active = true;
                     }
                 }
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
 
         if (active) {
             const State<double> xp = x;
-            const int fl = rk4_step(K, x);
+            const int fl = rk4_step(K, x, sth, cth);
             int32_t st = GRAY_RUNNING;
             if (fl < 0) {
                 st = GRAY_NONFINITE;
@@ -252,10 +253,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                     const double rc = xp.r + f * (x.r - xp.r);
                     if (rc >= dmin && rc <= dmax) {
                         double E, L, Q;
-                        conserved(K.a, x, E, L, Q);
+                        conserved(K.B.a, x, E, L, Q);
                         A.disk[0 * S + id] = rc;
                         A.disk[1 * S + id] = xp.ph + f * (x.ph - xp.ph);
-                        A.disk[2 * S + id] = disk_redshift(K.a, rc, E, L);
+                        A.disk[2 * S + id] = disk_redshift(K.B.a, rc, E, L);
                         hit = true;
                     }
                 }
@@ -323,7 +324,23 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassArgs A)
     const int64_t S = A.stride;
     const int32_t st = A.status[i];
     A.flag[i] = (int8_t)st;
-    if (A.counts) atomicAdd(&A.counts[c.index * 5 + (st >= 0 && st < 5 ? st : 4)], 1);
+    if (A.counts) {
+        // One atomic per wave and status when the wave's photons share a
+        // camera (the common case), else one per photon.
+        const int sb = (st >= 0 && st < 5) ? st : 4;
+        const int c0 = __builtin_amdgcn_readfirstlane(c.index);
+        if (ballot(c.index != c0) == 0ull) {
+            const uint64_t act = ballot(true);
+            const unsigned lane = threadIdx.x & (kWave - 1);
+            for (int k = 0; k < 5; ++k) {
+                const uint64_t m = ballot(sb == k);
+                if (m && lane == (unsigned)(__ffsll((long long)act) - 1))
+                    atomicAdd(&A.counts[c0 * 5 + k], (int)__popcll(m));
+            }
+        } else {
+            atomicAdd(&A.counts[c.index * 5 + sb], 1);
+        }
+    }
 
     State<double> xf;
     double v[8];

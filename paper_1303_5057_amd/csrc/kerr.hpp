@@ -55,57 +55,176 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
 constexpr double kHalfPi = 0.5 * 3.14159265358979323846;
 
-// Geodesic acceleration given sin and cos of theta (see the file comment).
-template <class T>
-GRAY_HD void accel(T a, T a2, T r, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr, T &dkth,
-                   T &dkph)
+// ------------------------------------------------------------ FP64 primitives
+// Reciprocal: the hardware estimate refined by two Newton-Raphson steps
+// (y <- y + y (1 - x y)), accurate to about one ulp for the magnitudes met
+// here (no denormals; 0 and inf give non-finite results).
+GRAY_HD double rcp(double x)
 {
-    const T two = T(2);
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+#else
+    return 1.0 / x;
+#endif
+}
+
+GRAY_HD double quot(double a, double b) { return a * rcp(b); }
+
+// sin and cos of a small angle, |d| <= 1/16, from their Taylor series (sin
+// to d^9, cos to d^8: truncation below 3e-19). The stage offsets of a step
+// obey |d| <= Delta of eq. (2) to first order, so this covers them.
+GRAY_HD void sincos_small(double d, double &sd, double &cd)
+{
+    const double z = d * d;
+    double ps = fma(z, 2.755731922398589e-06, -1.984126984126984e-04);
+    ps = fma(z, ps, 8.333333333333333e-03);
+    ps = fma(z, ps, -1.6666666666666666e-01);
+    sd = fma(d * z, ps, d);
+    double pc = fma(z, 2.48015873015873e-05, -1.388888888888889e-03);
+    pc = fma(z, pc, 4.1666666666666664e-02);
+    pc = fma(z, pc, -0.5);
+    cd = fma(z, pc, 1.0);
+}
+
+// sin and cos of a moderate angle (|x| << 2^20): Cody-Waite reduction by
+// pi/2 with a two-term split of pi/2 (FMA keeps the first subtraction exact),
+// then Taylor series on |r| <= pi/4 (sin to r^17, cos to r^18, truncation
+// below 1e-19), then the quadrant.
+GRAY_HD void sincos_full(double x, double &s, double &c)
+{
+    const double k = rint(x * 0.6366197723675814);
+    double r = fma(-k, 1.5707963267948966, x);
+    r = fma(-k, 6.123233995736766e-17, r);
+    const double z = r * r;
+    double ps = fma(z, 2.8114572543455206e-15, -7.647163731819816e-13);
+    ps = fma(z, ps, 1.6059043836821613e-10);
+    ps = fma(z, ps, -2.505210838544172e-08);
+    ps = fma(z, ps, 2.755731922398589e-06);
+    ps = fma(z, ps, -1.984126984126984e-04);
+    ps = fma(z, ps, 8.333333333333333e-03);
+    ps = fma(z, ps, -1.6666666666666666e-01);
+    const double sr = fma(r * z, ps, r);
+    double pc = fma(z, -1.5619206968586225e-16, 4.779477332387385e-14);
+    pc = fma(z, pc, -1.1470745597729725e-11);
+    pc = fma(z, pc, 2.08767569878681e-09);
+    pc = fma(z, pc, -2.755731922398589e-07);
+    pc = fma(z, pc, 2.48015873015873e-05);
+    pc = fma(z, pc, -1.388888888888889e-03);
+    pc = fma(z, pc, 4.1666666666666664e-02);
+    pc = fma(z, pc, -0.5);
+    const double cr = fma(z, pc, 1.0);
+    const int q = (int)k & 3;
+    const double a = (q & 1) ? cr : sr;
+    const double b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
+GRAY_HD void sin_cos(double x, double &s, double &c) { sincos_full(x, s, c); }
+
+// sin and cos of th = th0 + d from those of th0 (angle addition with the
+// small-angle series); falls back to the full evaluation when |d| > 1/16.
+GRAY_HD void shift_sincos(double s0, double c0, double d, double th, double &s, double &c)
+{
+    if (fabs(d) <= 0.0625) {
+        double sd, cd;
+        sincos_small(d, sd, cd);
+        s = fma(s0, cd, c0 * sd);
+        c = fma(c0, cd, -(s0 * sd));
+    } else {
+        sincos_full(th, s, c);
+    }
+}
+
+// Spin-dependent constants of one photon's spacetime.
+template <class T>
+struct Spin {
+    T a, a2, a_2, a_4, a2_2;   // a, a^2, 2a, 4a, 2a^2
+};
+
+template <class T>
+GRAY_HD Spin<T> make_spin(T a)
+{
+    Spin<T> B;
+    B.a = a;
+    B.a2 = a * a;
+    B.a_2 = T(2) * a;
+    B.a_4 = T(4) * a;
+    B.a2_2 = T(2) * B.a2;
+    return B;
+}
+
+// Geodesic acceleration given sin and cos of theta (see the file comment),
+// written out operation by operation: one reciprocal of Sigma Delta sin gives
+// 1/Sigma, 1/Delta and cot; every contraction is shaped into fused
+// multiply-adds.
+template <class T>
+GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr,
+                   T &dkth, T &dkph)
+{
+    const T a = B.a, a2 = B.a2;
     const T r2 = r * r;
     const T s2 = s * s;
     const T sc = s * c;
     const T sig = fma(a2, c * c, r2);
-    const T del = fma(r, r - two, a2);
+    const T del = fma(r, r - T(2), a2);
     const T rho2 = r2 + a2;
-    const T isig = T(1) / sig;
-    const T idel = T(1) / del;
-    const T cot = c / s;
+    const T sd = sig * del;
+    const T i3 = rcp(sd * s);
+    const T si3 = s * i3;
+    const T isig = del * si3;
+    const T idel = sig * si3;
+    const T cot = c * (sd * i3);
     const T q = r * isig;
-    const T w = isig - two * q * q;
+    const T w = fma(T(-2) * q, q, isig);
     const T W = rho2 * isig;
-    const T F = fma(two * a2 * s2, q, rho2);
-    const T grr = sig * idel;
-    const T drgrr = idel * (two * r - grr * (two * r - two));
-    const T P = kt - a * s2 * kph;
+    const T F = fma(B.a2_2 * s2, q, rho2);
+    const T hdrgrr = idel * fma(-(sig * idel), r - T(1), r);   // (1/2) d_r g_rr
+    const T P = fma(-(a * s2), kph, kt);
+    const T kr2 = kr * kr, kth2 = kth * kth, kph2 = kph * kph;
 
-    const T At = two * w * kr * P + T(4) * a * q * sc * kth * (a * isig * kt - W * kph);
-    const T Aph = kr * (two * r * kph - two * a * w * P) +
-                  kth * (two * F * cot * kph - T(4) * a * q * W * (cot * kt - a * sc * kph));
-    const T Ar = T(0.5) * drgrr * kr * kr - two * a2 * sc * idel * kr * kth -
-                 r * (kth * kth + s2 * kph * kph) - w * P * P;
-    const T Ath = two * r * kr * kth +
-                  sc * (a2 * (idel * kr * kr - kth * kth) - F * kph * kph -
-                        two * q * (a2 * isig * kt * kt - two * a * W * kt * kph + a2 * s2 * W * kph * kph));
+    // A_t
+    const T X = fma(a * isig, kt, -(W * kph));
+    const T At = fma((w + w) * kr, P, ((B.a_4 * (q * sc)) * kth) * X);
+    // A_phi / sin^2
+    const T t1 = fma(-(a * w), P, r * kph);
+    const T u = fma(-(a * sc), kph, cot * kt);
+    const T Fc = F * cot;
+    const T inner = fma(-(B.a_4 * (q * W)), u, (Fc + Fc) * kph);
+    const T Aph = fma(kth, inner, (kr + kr) * t1);
+    // A_r
+    T Ar = hdrgrr * kr2;
+    Ar = fma(-((B.a2_2 * sc) * idel * kr), kth, Ar);
+    Ar = fma(-r, fma(s2, kph2, kth2), Ar);
+    Ar = fma(-(w * P), P, Ar);
+    // A_theta
+    T e = (a2 * isig) * (kt * kt);
+    e = fma(-((B.a_2 * W) * kt), kph, e);
+    e = fma((a2 * s2) * W, kph2, e);
+    T g = a2 * fma(idel, kr2, -kth2);
+    g = fma(-F, kph2, g);
+    g = fma(-(q + q), e, g);
+    const T Ath = fma(sc, g, ((r + r) * kr) * kth);
 
-    dkt = (F * At + two * a * q * s2 * Aph) * idel;
-    dkr = -Ar * del * isig;
+    dkt = fma((B.a_2 * q) * s2, Aph, F * At) * idel;
+    dkr = -Ar * (del * isig);
     dkth = -Ath * isig;
-    dkph = ((two * q - T(1)) * Aph + two * a * q * At) * idel;
+    dkph = fma((q + q) - T(1), Aph, (B.a_2 * q) * At) * idel;
 }
 
-// sin and cos of an angle; overloaded per arithmetic type.
-GRAY_HD void sin_cos(double x, double &s, double &c) { sincos(x, &s, &c); }
-
+// f(y) of the geodesic equation given sin and cos of y.th.
 template <class T>
-GRAY_HD void deriv(T a, T a2, const State<T> &y, State<T> &f)
+GRAY_HD void deriv(const Spin<T> &B, const State<T> &y, T s, T c, State<T> &f)
 {
-    T s, c;
-    sin_cos(y.th, s, c);
     f.t = y.kt;
     f.r = y.kr;
     f.th = y.kth;
     f.ph = y.kph;
-    accel(a, a2, y.r, s, c, y.kt, y.kr, y.kth, y.kph, f.kt, f.kr, f.kth, f.kph);
+    accel(B, y.r, s, c, y.kt, y.kr, y.kth, y.kph, f.kt, f.kr, f.kth, f.kph);
 }
 
 template <class T>
@@ -135,11 +254,12 @@ GRAY_HD Metric<T> metric(T a, T a2, T r, T s, T c)
     const T s2 = s * s;
     const T sig = fma(a2, c * c, r * r);
     const T del = fma(r, r - T(2), a2);
-    const T q = r / sig;
+    const T i2 = rcp(sig * del);
+    const T q = r * (del * i2);
     Metric<T> g;
     g.tt = T(2) * q - T(1);
     g.tph = T(-2) * a * q * s2;
-    g.rr = sig / del;
+    g.rr = sig * (sig * i2);
     g.thth = sig;
     g.phph = fma(T(2) * a2 * s2, q, r * r + a2) * s2;
     return g;
@@ -158,41 +278,57 @@ GRAY_HD bool xi_violated(const Metric<T> &g, T kt, T kr, T kth, T kph, T eps)
 // Integrator constants of one photon.
 template <class T>
 struct StepConst {
-    T a, a2, rbh, step_frac, xi_eps, euler_div;
+    Spin<T> B;
+    T rbh, step_frac, xi_eps, euler_div;
 };
 
 // One accepted step of the production scheme (Sec. 2): classical RK4 with h
 // from eq. (2); if the proposal violates the null condition, |xi + 1| > eps
 // (eq. 4), one forward-Euler step of h / euler_div from the same start
-// replaces it; then the remap of eq. (3). Returns bit 0 = Euler fallback,
-// bit 1 = remap, or -1 when h is not a positive finite number (state kept).
+// replaces it; then the remap of eq. (3). (s, c) = sin/cos(x.th) on entry and
+// on exit (always recomputed from the final theta, so a step is a function of
+// the stored state alone). Returns bit 0 = Euler fallback, bit 1 = remap, or
+// -1 when h is not a positive finite number (state kept).
 template <class T>
-GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x)
+GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
 {
-    const T h1 = K.step_frac / (fabs(x.kr) / x.r + fabs(x.kth) + fabs(x.kph));
-    const T h2 = (x.kr != T(0)) ? (x.r - K.rbh) / (T(2) * fabs(x.kr)) : T(INFINITY);
-    const T h = h2 < h1 ? h2 : h1;
+    // eq. (2): h1 = Delta r / D1 with D1 = |k^r| + r (|k^th| + |k^ph|), and
+    // h2 = (r - r_bh) / (2 |k^r|); h2 < h1 is decided without dividing.
+    const T akr = fabs(x.kr);
+    const T D1 = fma(x.r, fabs(x.kth) + fabs(x.kph), akr);
+    const T n1 = K.step_frac * x.r;
+    const T n2 = x.r - K.rbh;
+    const T d2 = akr + akr;
+    const bool second = (x.kr != T(0)) && (n2 * D1 < d2 * n1);
+    const T h = second ? quot(n2, d2) : quot(n1, D1);
     if (!(h > T(0) && h < T(INFINITY))) return -1;
+    const T hh = T(0.5) * h;
 
-    State<T> k1, k2, k3, k4;
-    deriv(K.a, K.a2, x, k1);
-    deriv(K.a, K.a2, axpy(x, T(0.5) * h, k1), k2);
-    deriv(K.a, K.a2, axpy(x, T(0.5) * h, k2), k3);
-    deriv(K.a, K.a2, axpy(x, h, k3), k4);
+    State<T> k1, k2, k3, k4, y;
+    T sy, cy;
+    deriv(K.B, x, s, c, k1);
+    y = axpy(x, hh, k1);
+    shift_sincos(s, c, y.th - x.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k2);
+    y = axpy(x, hh, k2);
+    shift_sincos(s, c, y.th - x.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k3);
+    y = axpy(x, h, k3);
+    shift_sincos(s, c, y.th - x.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k4);
 
     const T h6 = h * T(1.0 / 6.0);
     State<T> xn;
-#define GRAY_RK4(c) xn.c = fma(h6, k1.c + T(2) * (k2.c + k3.c) + k4.c, x.c)
+#define GRAY_RK4(cmp) xn.cmp = fma(h6, k1.cmp + T(2) * (k2.cmp + k3.cmp) + k4.cmp, x.cmp)
     GRAY_RK4(t); GRAY_RK4(r); GRAY_RK4(th); GRAY_RK4(ph);
     GRAY_RK4(kt); GRAY_RK4(kr); GRAY_RK4(kth); GRAY_RK4(kph);
 #undef GRAY_RK4
 
     int flags = 0;
-    T s, c;
-    sin_cos(xn.th, s, c);
-    const Metric<T> g = metric(K.a, K.a2, xn.r, s, c);
+    sin_cos(xn.th, sy, cy);
+    const Metric<T> g = metric(K.B.a, K.B.a2, xn.r, sy, cy);
     if (xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps)) {
-        xn = axpy(x, h / K.euler_div, k1);
+        xn = axpy(x, quot(h, K.euler_div), k1);
         flags |= 1;
     }
     if (xn.th > T(kPi)) {
@@ -206,7 +342,10 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x)
         xn.kth = -xn.kth;
         flags |= 2;
     }
+    if (flags) sin_cos(xn.th, sy, cy);
     x = xn;
+    s = sy;
+    c = cy;
     return flags;
 }
 
