@@ -73,6 +73,50 @@ def cpu_baseline(cam, params, every: int):
                       f"({len(ids)} rays, {nsteps} photon-steps, {dt:.2f} s wall)"}
 
 
+def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
+    """Time `steps` passes (camera_init + integrate + classify) after `warmup`."""
+    params = W.Params(precision=prec)
+    b = G.Batch([cam], params)
+
+    def one_pass(ev0=None, ev1=None):
+        b.camera_init()
+        if ev0 is not None:
+            ev0.record()
+        b.integrate()
+        if ev1 is not None:
+            ev1.record()
+        return b.classify(xf=False, cons=True, counts=True)
+
+    for _ in range(warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        res = one_pass(e0, e1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    int_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    total_steps = int(b.steps[: b.n].to(torch.int64).sum().item())
+    counters = b.counters.view(3, b.stride)[:, : b.n].to(torch.int64).sum(dim=1).tolist()
+    status = b.status[: b.n].cpu().numpy()
+    cons = res.cons.view(9, b.stride)[:, : b.n].cpu().numpy()
+    euler = b.counters.view(3, b.stride)[0, : b.n].cpu().numpy()
+    drift = {}
+    for name, sel in (("escaped", status == G.ESCAPED), ("captured", status == G.CAPTURED),
+                      ("no_fallback", euler == 0)):
+        d = cons[6:9, sel]
+        drift[name] = {q: np.percentile(d, pq, axis=1).tolist()
+                       for q, pq in (("p50", 50), ("p99", 99), ("max", 100))} if d.size else {}
+    return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
+            "total_steps": total_steps, "status": np.bincount(status, minlength=5).tolist(),
+            "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -89,73 +133,51 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 3
     cam = W.C2
-    params = W.Params(precision=args.precision)
-    b = G.Batch([cam], params)
+    head = measure(G, W, torch, np, cam, args.precision, args.steps, args.warmup)
+    other_prec = "fp32c" if args.precision == "fp64" else "fp64"
+    other = measure(G, W, torch, np, cam, other_prec, args.steps, args.warmup)
+    t64 = head["integrate_ms"] if args.precision == "fp64" else other["integrate_ms"]
+    t32 = other["integrate_ms"] if args.precision == "fp64" else head["integrate_ms"]
 
-    def one_pass(ev0=None, ev1=None):
-        b.camera_init()
-        if ev0 is not None:
-            ev0.record()
-        b.integrate()
-        if ev1 is not None:
-            ev1.record()
-        return b.classify(xf=False, cons=True, counts=True)
-
-    for _ in range(args.warmup):
-        one_pass()
-    torch.cuda.synchronize()
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in evs:
-        res = one_pass(e0, e1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    int_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
-    steps = b.steps[: b.n].to(torch.int64)
-    total_steps = int(steps.sum().item())
-    status = b.status[: b.n].cpu().numpy()
-    cons = res.cons.view(9, b.stride)[:, : b.n].cpu().numpy()
-    drift = {}
-    for name, sel in (("escaped", status == G.ESCAPED), ("captured", status == G.CAPTURED)):
-        d = cons[6:9, sel]
-        drift[name] = {q: np.percentile(d, pq, axis=1).tolist()
-                       for q, pq in (("p50", 50), ("p99", 99), ("max", 100))} if d.size else {}
-    achieved = F_STEP[args.precision] * total_steps / (int_ms * 1e-3) / 1e12
+    total_steps = head["total_steps"]
+    achieved = F_STEP[args.precision] * total_steps / (head["integrate_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-
+    kernel = "k_integrate<GRAY_FP64>" if args.precision == "fp64" else "k_integrate<GRAY_FP32C>"
     out = {
         "metric": "ns/photon/step",
-        "value": ms_per_step * 1e6 / total_steps,
+        "value": head["ms_per_step"] * 1e6 / total_steps,
         "unit": "ns/photon/step",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f32c",
         "data": "synthetic",
-        "config": {"workload": "kerr_a0.99_i90_512x512_r1000", "photons": b.n,
+        "config": {"workload": "kerr_a0.99_i90_512x512_r1000", "photons": head["n"],
                    "grid": [cam.nx, cam.ny], "spin": cam.a, "incl_deg": 90.0,
-                   "precision": args.precision, "step_frac": params.step_frac},
+                   "precision": args.precision, "step_frac": head["params"].step_frac},
         "photon_steps_per_pass": total_steps,
-        "photon_steps_per_s": total_steps / (ms_per_step * 1e-3),
-        "integrate_ms": int_ms,
-        "integrate_ns_per_photon_step": int_ms * 1e6 / total_steps,
-        "status_counts": np.bincount(status, minlength=5).tolist(),
-        "drift_ELQ": drift,
+        "photon_steps_per_s": total_steps / (head["ms_per_step"] * 1e-3),
+        "integrate_ms": head["integrate_ms"],
+        "integrate_ns_per_photon_step": head["integrate_ms"] * 1e6 / total_steps,
+        "status_counts": head["status"],
+        "euler_fallback_steps": head["euler_steps"],
+        "drift_ELQ": head["drift"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_integrate_fp64", "flops_per_photon_step": F_STEP[args.precision]},
+                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "flops_per_photon_step": F_STEP[args.precision]},
+        other_prec: {"ns_per_photon_step": other["ms_per_step"] * 1e6 / other["total_steps"],
+                     "integrate_ms": other["integrate_ms"],
+                     "photon_steps_per_pass": other["total_steps"],
+                     "fp64_step_fraction": other["fp64_steps"] / other["total_steps"],
+                     "status_counts": other["status"], "drift_ELQ": other["drift"]},
+        "fp32c_speedup_vs_fp64": t64 / t32,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cam, params, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(cam, head["params"], args.cpu_sample)
     print(json.dumps(out), flush=True)
     return 0
 

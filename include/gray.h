@@ -108,6 +108,12 @@ typedef struct {
     double euler_div;    /* Euler fallback step h / euler_div; 9 in Sec. 2  >= 1 */
     double disk_rmin;    /* recorder window [rmin, rmax]; rmin < 0: r_ISCO(a)     */
     double disk_rmax;
+    /* GRAY_FP32C only: a step runs in double precision while any of these
+     * holds (near the horizon, near a pole, near a radial turning point);
+     * all >= 0, e.g. 1, 0.05, 0.01.                                          */
+    double fp64_horizon; /* r < r_bh (1 + fp64_horizon)                          */
+    double fp64_pole;    /* sin(theta) < fp64_pole                                */
+    double fp64_turn;    /* |k^r| < fp64_turn |k^t|                               */
     int32_t max_steps;   /* total accepted steps before GRAY_UNFINISHED     >= 1 */
     int32_t call_steps;  /* > 0: advance each photon at most this many steps in
                             this call and leave it GRAY_RUNNING (resumable);

@@ -145,15 +145,10 @@ __global__ void k_setup(DevCam *table, unsigned *queue, SetupChunk ch)
     if (ch.base == 0 && j == 0) *queue = 0u;
 }
 
-__device__ __forceinline__ bool finite_state(const State<double> &x)
-{
-    return isfinite(x.t) && isfinite(x.r) && isfinite(x.th) && isfinite(x.ph) && isfinite(x.kt) &&
-           isfinite(x.kr) && isfinite(x.kth) && isfinite(x.kph);
-}
 
 // ------------------------------------------------------- persistent integrator
 struct IntArgs {
-    double *x;
+    void *x, *lo;
     int32_t *status, *steps;
     const int32_t *cam;
     int32_t *counters;
@@ -162,12 +157,95 @@ struct IntArgs {
     unsigned *queue;
     int64_t n, stride;
     double step_frac, xi_eps, euler_div, r_escape;
+    double fp64_horizon, fp64_pole, fp64_turn;
     int32_t max_steps, call_steps;
     uint32_t flags;
     int32_t refill;
 };
 
-__global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
+// Per-lane photon of the persistent loop. In FP64 the state is x; in FP32C
+// it is hi + lo (floats) and x is not kept between steps.
+template <int P>
+struct Lane;
+
+template <>
+struct Lane<GRAY_FP64> {
+    State<double> x;
+    double s, c;
+    __device__ __forceinline__ void load(const IntArgs &A, int64_t id)
+    {
+        const double *X = (const double *)A.x;
+        const int64_t S = A.stride;
+        x.t = X[0 * S + id]; x.r = X[1 * S + id]; x.th = X[2 * S + id]; x.ph = X[3 * S + id];
+        x.kt = X[4 * S + id]; x.kr = X[5 * S + id]; x.kth = X[6 * S + id]; x.kph = X[7 * S + id];
+        sin_cos(x.th, s, c);
+    }
+    __device__ __forceinline__ void store(const IntArgs &A, int64_t id) const
+    {
+        double *X = (double *)A.x;
+        const int64_t S = A.stride;
+        X[0 * S + id] = x.t; X[1 * S + id] = x.r; X[2 * S + id] = x.th; X[3 * S + id] = x.ph;
+        X[4 * S + id] = x.kt; X[5 * S + id] = x.kr; X[6 * S + id] = x.kth; X[7 * S + id] = x.kph;
+    }
+    __device__ __forceinline__ State<double> value() const { return x; }
+};
+
+template <>
+struct Lane<GRAY_FP32C> {
+    State<float> hi, lo;
+    float s, c;
+    __device__ __forceinline__ void load(const IntArgs &A, int64_t id)
+    {
+        const float *H = (const float *)A.x, *L = (const float *)A.lo;
+        const int64_t S = A.stride;
+        hi.t = H[0 * S + id]; hi.r = H[1 * S + id]; hi.th = H[2 * S + id]; hi.ph = H[3 * S + id];
+        hi.kt = H[4 * S + id]; hi.kr = H[5 * S + id]; hi.kth = H[6 * S + id]; hi.kph = H[7 * S + id];
+        lo.t = L[0 * S + id]; lo.r = L[1 * S + id]; lo.th = L[2 * S + id]; lo.ph = L[3 * S + id];
+        lo.kt = L[4 * S + id]; lo.kr = L[5 * S + id]; lo.kth = L[6 * S + id]; lo.kph = L[7 * S + id];
+        sin_cos(hi.th, s, c);
+    }
+    __device__ __forceinline__ void store(const IntArgs &A, int64_t id) const
+    {
+        float *H = (float *)A.x, *L = (float *)A.lo;
+        const int64_t S = A.stride;
+        H[0 * S + id] = hi.t; H[1 * S + id] = hi.r; H[2 * S + id] = hi.th; H[3 * S + id] = hi.ph;
+        H[4 * S + id] = hi.kt; H[5 * S + id] = hi.kr; H[6 * S + id] = hi.kth; H[7 * S + id] = hi.kph;
+        L[0 * S + id] = lo.t; L[1 * S + id] = lo.r; L[2 * S + id] = lo.th; L[3 * S + id] = lo.ph;
+        L[4 * S + id] = lo.kt; L[5 * S + id] = lo.kr; L[6 * S + id] = lo.kth; L[7 * S + id] = lo.kph;
+    }
+    __device__ __forceinline__ State<double> value() const
+    {
+        State<double> x;
+        x.t = (double)hi.t + (double)lo.t; x.r = (double)hi.r + (double)lo.r;
+        x.th = (double)hi.th + (double)lo.th; x.ph = (double)hi.ph + (double)lo.ph;
+        x.kt = (double)hi.kt + (double)lo.kt; x.kr = (double)hi.kr + (double)lo.kr;
+        x.kth = (double)hi.kth + (double)lo.kth; x.kph = (double)hi.kph + (double)lo.kph;
+        return x;
+    }
+    __device__ __forceinline__ void set(const State<double> &x)
+    {
+#define GRAY_SPLIT(cmp) hi.cmp = (float)x.cmp; lo.cmp = (float)(x.cmp - (double)hi.cmp)
+        GRAY_SPLIT(t); GRAY_SPLIT(r); GRAY_SPLIT(th); GRAY_SPLIT(ph);
+        GRAY_SPLIT(kt); GRAY_SPLIT(kr); GRAY_SPLIT(kth); GRAY_SPLIT(kph);
+#undef GRAY_SPLIT
+        sin_cos(hi.th, s, c);
+    }
+};
+
+__device__ __forceinline__ bool finite_state(const State<double> &x)
+{
+    return isfinite(x.t) && isfinite(x.r) && isfinite(x.th) && isfinite(x.ph) && isfinite(x.kt) &&
+           isfinite(x.kr) && isfinite(x.kth) && isfinite(x.kph);
+}
+
+// Persistent integrator. Each wave keeps 64 photons in registers; whenever at
+// least A.refill lanes are idle it hands them the next photons of the wave's
+// current 64-photon chunk, taking a new chunk from the global counter when the
+// old one is used up. A wave exits once the counter is past n and all its
+// lanes are idle; every photon ends within max_steps (or call_steps) steps,
+// so every wave exits.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
     const unsigned lane = threadIdx.x & (kWave - 1);
     const int64_t S = A.stride;
@@ -175,11 +253,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
 
     bool active = false;
     int64_t id = 0;
-    State<double> x;
+    Lane<P> L;
     StepConst<double> K;
+    StepConst<float> Kf;
     double rcap = 0.0, rmark = 0.0, dmin = 0.0, dmax = 0.0;
-    double sth = 0.0, cth = 1.0;
-    int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0;
+    float r64 = 0.0f;
+    int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
 
     unsigned chunk_next = 0, chunk_end = 0;
@@ -201,22 +280,22 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                 const unsigned rank = lane_rank(idle);
                 if (!active && rank < avail) {
                     id = (int64_t)(chunk_next + rank);
-                    const int32_t st = A.status[id];
-                    if (st == GRAY_RUNNING) {
-                        x.t = A.x[0 * S + id];
-                        x.r = A.x[1 * S + id];
-                        x.th = A.x[2 * S + id];
-                        x.ph = A.x[3 * S + id];
-                        x.kt = A.x[4 * S + id];
-                        x.kr = A.x[5 * S + id];
-                        x.kth = A.x[6 * S + id];
-                        x.kph = A.x[7 * S + id];
+                    if (A.status[id] == GRAY_RUNNING) {
+                        L.load(A, id);
                         const DevCam cm = A.cams[A.cam[id]];
                         K.B = make_spin(cm.a);
                         K.rbh = cm.rbh;
                         K.step_frac = A.step_frac;
                         K.xi_eps = A.xi_eps;
                         K.euler_div = A.euler_div;
+                        if constexpr (P == GRAY_FP32C) {
+                            Kf.B = make_spin((float)cm.a);
+                            Kf.rbh = (float)cm.rbh;
+                            Kf.step_frac = (float)A.step_frac;
+                            Kf.xi_eps = (float)(0.5 * A.xi_eps);
+                            Kf.euler_div = (float)A.euler_div;
+                            r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
+                        }
                         rcap = cm.rcap;
                         rmark = cm.rmark;
                         dmin = cm.disk_rmin;
@@ -225,8 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                         ncall = 0;
                         ne = A.counters ? A.counters[0 * S + id] : 0;
                         nr = A.counters ? A.counters[1 * S + id] : 0;
+                        n64 = A.counters ? A.counters[2 * S + id] : 0;
                         hit = record_disk && A.disk[0 * S + id] != 0.0;
-                        sin_cos(x.th, sth, cth);
                         active = true;
                     }
                 }
@@ -237,8 +316,30 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
         }
 
         if (active) {
-            const State<double> xp = x;
-            const int fl = rk4_step(K, x, sth, cth);
+            const State<double> xp = L.value();
+            State<double> x;
+            int fl;
+            if constexpr (P == GRAY_FP64) {
+                fl = rk4_step(K, L.x, L.s, L.c);
+                x = L.x;
+            } else {
+                auto &F = L;
+                const bool need64 = F.hi.r < r64 || F.s < (float)A.fp64_pole ||
+                                    fabsf(F.hi.kr) < (float)A.fp64_turn * fabsf(F.hi.kt);
+                fl = -2;
+                if (!need64) fl = rk4_step_c32(Kf, F.hi, F.lo, F.s, F.c, Kf.xi_eps);
+                if (fl == -2) {
+                    x = xp;
+                    double s64, c64;
+                    sin_cos(x.th, s64, c64);
+                    fl = rk4_step(K, x, s64, c64);
+                    if (fl >= 0) {
+                        F.set(x);
+                        ++n64;
+                    }
+                }
+                x = F.value();
+            }
             int32_t st = GRAY_RUNNING;
             if (fl < 0) {
                 st = GRAY_NONFINITE;
@@ -247,16 +348,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                 ++ncall;
                 ne += fl & 1;
                 nr += (fl >> 1) & 1;
-                if (record_disk && !hit &&
-                    (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0) {
+                if (record_disk && !hit && (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0) {
                     const double f = (kHalfPi - xp.th) / (x.th - xp.th);
                     const double rc = xp.r + f * (x.r - xp.r);
                     if (rc >= dmin && rc <= dmax) {
-                        double E, L, Q;
-                        conserved(K.B.a, x, E, L, Q);
+                        double E, Lz, Q;
+                        conserved(K.B.a, x, E, Lz, Q);
                         A.disk[0 * S + id] = rc;
                         A.disk[1 * S + id] = xp.ph + f * (x.ph - xp.ph);
-                        A.disk[2 * S + id] = disk_redshift(K.B.a, rc, E, L);
+                        A.disk[2 * S + id] = disk_redshift(K.B.a, rc, E, Lz);
                         hit = true;
                     }
                 }
@@ -276,19 +376,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate_fp64(IntArgs A)
                 else if (nsteps >= A.max_steps) st = GRAY_UNFINISHED;
             }
             if (st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps)) {
-                A.x[0 * S + id] = x.t;
-                A.x[1 * S + id] = x.r;
-                A.x[2 * S + id] = x.th;
-                A.x[3 * S + id] = x.ph;
-                A.x[4 * S + id] = x.kt;
-                A.x[5 * S + id] = x.kr;
-                A.x[6 * S + id] = x.kth;
-                A.x[7 * S + id] = x.kph;
+                L.store(A, id);
                 A.status[id] = st;
                 A.steps[id] = nsteps;
                 if (A.counters) {
                     A.counters[0 * S + id] = ne;
                     A.counters[1 * S + id] = nr;
+                    A.counters[2 * S + id] = n64;
                 }
                 active = false;
             }
@@ -397,6 +491,9 @@ static int validate_params(const gray_params *p)
     if (p->max_steps < 1 || p->call_steps < 0) return GRAY_EINVAL;
     if (p->precision != GRAY_FP64 && p->precision != GRAY_FP32C) return GRAY_EINVAL;
     if (p->flags & ~GRAY_RECORD_DISK) return GRAY_EINVAL;
+    if (!(p->fp64_horizon >= 0.0 && std::isfinite(p->fp64_horizon))) return GRAY_EINVAL;
+    if (!(p->fp64_pole >= 0.0 && std::isfinite(p->fp64_pole))) return GRAY_EINVAL;
+    if (!(p->fp64_turn >= 0.0 && std::isfinite(p->fp64_turn))) return GRAY_EINVAL;
     if (p->flags & GRAY_RECORD_DISK) {
         if (!(p->disk_rmax > 0.0) || std::isnan(p->disk_rmin)) return GRAY_EINVAL;
     }
@@ -462,7 +559,7 @@ static void fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, CamChun
 
 struct DeviceInfo {
     int cus = 0;
-    int blocks_per_cu_fp64 = 0;
+    int blocks_per_cu[2] = {0, 0};
 };
 static std::mutex g_dev_mutex;
 static DeviceInfo g_dev[64];
@@ -480,9 +577,12 @@ static int device_info(DeviceInfo &out)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
         int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate_fp64, kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<GRAY_FP64>, kBlock, 0);
         if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-        d.blocks_per_cu_fp64 = nb > 0 ? nb : 1;
+        d.blocks_per_cu[GRAY_FP64] = nb > 0 ? nb : 1;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<GRAY_FP32C>, kBlock, 0);
+        if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+        d.blocks_per_cu[GRAY_FP32C] = nb > 0 ? nb : 1;
         d.cus = cus;
     }
     out = d;
@@ -509,7 +609,6 @@ extern "C" int gray_camera_init(const gray_camera *cams, int32_t ncam, const gra
     if ((e = validate_state(s, p))) return e;
     if (s->n == 0) return GRAY_OK;
     if ((e = validate_cameras(cams, ncam, s->n))) return e;
-    if (p->precision != GRAY_FP64) return GRAY_EUNSUPPORTED;
     hipStream_t st = (hipStream_t)hip_stream;
     for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
         InitArgs A;
@@ -544,7 +643,6 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     if (!workspace || ((uintptr_t)workspace & 255u) != 0 ||
         workspace_bytes < gray_workspace_size(s->n, ncam, p))
         return GRAY_EWORKSPACE;
-    if (p->precision != GRAY_FP64) return GRAY_EUNSUPPORTED;
 
     DeviceInfo dev;
     if ((e = device_info(dev))) return e;
@@ -574,7 +672,8 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
 
     IntArgs A;
     memset(&A, 0, sizeof A);
-    A.x = (double *)s->x;
+    A.x = s->x;
+    A.lo = s->lo;
     A.status = s->status;
     A.steps = s->steps;
     A.cam = s->cam;
@@ -589,14 +688,20 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.xi_eps = p->xi_eps;
     A.euler_div = p->euler_div;
     A.r_escape = p->r_escape;
+    A.fp64_horizon = p->fp64_horizon;
+    A.fp64_pole = p->fp64_pole;
+    A.fp64_turn = p->fp64_turn;
     A.max_steps = p->max_steps;
     A.call_steps = p->call_steps;
     A.flags = p->flags;
     A.refill = 1;
-    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu_fp64;
+    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[p->precision];
     const int64_t need = blocks_for(s->n);
     const unsigned grid = (unsigned)(need < resident ? need : resident);
-    hipLaunchKernelGGL(k_integrate_fp64, dim3(grid), dim3(kBlock), 0, st, A);
+    if (p->precision == GRAY_FP64)
+        hipLaunchKernelGGL(k_integrate<GRAY_FP64>, dim3(grid), dim3(kBlock), 0, st, A);
+    else
+        hipLaunchKernelGGL(k_integrate<GRAY_FP32C>, dim3(grid), dim3(kBlock), 0, st, A);
     return check_launch("integrate launch");
 }
 

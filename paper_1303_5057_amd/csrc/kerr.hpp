@@ -140,6 +140,66 @@ GRAY_HD void shift_sincos(double s0, double c0, double d, double th, double &s, 
     }
 }
 
+// ------------------------------------------------------------ FP32 primitives
+// Reciprocal: the hardware v_rcp_f32 (about one ulp, denormals flushed).
+GRAY_HD float rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+GRAY_HD float quot(float a, float b) { return a * rcp(b); }
+
+// sin and cos of |d| <= 1/16 (sin to d^5, cos to d^4: truncation < 1e-10).
+GRAY_HD void sincos_small(float d, float &sd, float &cd)
+{
+    const float z = d * d;
+    sd = fma(d * z, fma(z, 0.008333333767950535f, -0.1666666716337204f), d);
+    cd = fma(z, fma(z, 0.0416666679084301f, -0.5f), 1.0f);
+}
+
+// sin and cos of a moderate float angle: reduction by pi/2 with a two-term
+// float split of pi/2, then Taylor series on |r| <= pi/4 (sin to r^9, cos to
+// r^10: truncation below 3e-9).
+GRAY_HD void sincos_full(float x, float &s, float &c)
+{
+    const float k = rintf(x * 0.6366197466850281f);
+    float r = fma(-k, 1.5707963705062866f, x);
+    r = fma(-k, -4.371138828673793e-08f, r);
+    const float z = r * r;
+    float ps = fma(z, 2.7557318844628753e-06f, -0.00019841270113829523f);
+    ps = fma(z, ps, 0.008333333767950535f);
+    ps = fma(z, ps, -0.1666666716337204f);
+    const float sr = fma(r * z, ps, r);
+    float pc = fma(z, -2.755731998149713e-07f, 2.4801587642286904e-05f);
+    pc = fma(z, pc, -0.0013888889225199819f);
+    pc = fma(z, pc, 0.0416666679084301f);
+    pc = fma(z, pc, -0.5f);
+    const float cr = fma(z, pc, 1.0f);
+    const int q = (int)k & 3;
+    const float a = (q & 1) ? cr : sr;
+    const float b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
+GRAY_HD void sin_cos(float x, float &s, float &c) { sincos_full(x, s, c); }
+
+GRAY_HD void shift_sincos(float s0, float c0, float d, float th, float &s, float &c)
+{
+    if (fabsf(d) <= 0.0625f) {
+        float sd, cd;
+        sincos_small(d, sd, cd);
+        s = fma(s0, cd, c0 * sd);
+        c = fma(c0, cd, -(s0 * sd));
+    } else {
+        sincos_full(th, s, c);
+    }
+}
+
 // Spin-dependent constants of one photon's spacetime.
 template <class T>
 struct Spin {
@@ -347,6 +407,71 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
     s = sy;
     c = cy;
     return flags;
+}
+
+// Error-free sum of two floats (Knuth's TwoSum): hi + lo == a + b exactly.
+GRAY_HD void two_sum(float a, float b, float &hi, float &lo)
+{
+    const float t = a + b;
+    const float z = t - a;
+    lo = (a - (t - z)) + (b - z);
+    hi = t;
+}
+
+// One FP32 step of the compensated path. The state is hi + lo per component;
+// the RK4 stages run in float on hi alone, and the increment h/6 (k1 + 2 k2 +
+// 2 k3 + k4) is added to hi + lo with an error-free TwoSum, so the state keeps
+// about twice float precision while the right-hand sides are evaluated in
+// float. (s, c) = sin/cos(hi.th) on entry and exit. The proposal is accepted
+// only when it stays inside [0, pi] and satisfies |xi + 1| <= guard (in float,
+// guard < epsilon of eq. 4); otherwise the step returns -2 with the state
+// unchanged and the caller redoes it in FP64, so that every Euler-fallback
+// and remap decision of eq. (3)-(4) is taken in double precision.
+template <class T = float>
+GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<float> &lo, float &s,
+                         float &c, float guard)
+{
+    const float akr = fabsf(hi.kr);
+    const float D1 = fma(hi.r, fabsf(hi.kth) + fabsf(hi.kph), akr);
+    const float n1 = K.step_frac * hi.r;
+    const float n2 = hi.r - K.rbh;
+    const float d2 = akr + akr;
+    const bool second = (hi.kr != 0.0f) && (n2 * D1 < d2 * n1);
+    const float h = second ? quot(n2, d2) : quot(n1, D1);
+    if (!(h > 0.0f && h < INFINITY)) return -2;
+    const float hh = 0.5f * h;
+
+    State<float> k1, k2, k3, k4, y;
+    float sy, cy;
+    deriv(K.B, hi, s, c, k1);
+    y = axpy(hi, hh, k1);
+    shift_sincos(s, c, y.th - hi.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k2);
+    y = axpy(hi, hh, k2);
+    shift_sincos(s, c, y.th - hi.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k3);
+    y = axpy(hi, h, k3);
+    shift_sincos(s, c, y.th - hi.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k4);
+
+    const float h6 = h * (1.0f / 6.0f);
+    State<float> nh, nl;
+#define GRAY_C32(cmp) two_sum(hi.cmp, fma(h6, k1.cmp + 2.0f * (k2.cmp + k3.cmp) + k4.cmp, lo.cmp), nh.cmp, nl.cmp)
+    GRAY_C32(t); GRAY_C32(r); GRAY_C32(th); GRAY_C32(ph);
+    GRAY_C32(kt); GRAY_C32(kr); GRAY_C32(kth); GRAY_C32(kph);
+#undef GRAY_C32
+    if (!(nh.th >= 0.0f && nh.th <= float(kPi))) return -2;
+    if (!(isfinite(nh.t) && isfinite(nh.r) && isfinite(nh.ph) && isfinite(nh.kt) &&
+          isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph)))
+        return -2;
+    sin_cos(nh.th, sy, cy);
+    const Metric<float> g = metric(K.B.a, K.B.a2, nh.r, sy, cy);
+    if (xi_violated(g, nh.kt, nh.kr, nh.kth, nh.kph, guard)) return -2;
+    hi = nh;
+    lo = nl;
+    s = sy;
+    c = cy;
+    return 0;
 }
 
 // Initial state of the ray through image-plane point (alpha, beta) of an

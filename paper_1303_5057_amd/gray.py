@@ -41,7 +41,9 @@ class gray_params(ctypes.Structure):
     _fields_ = [("step_frac", ctypes.c_double), ("horizon_eps", ctypes.c_double),
                 ("r_escape", ctypes.c_double), ("xi_eps", ctypes.c_double),
                 ("euler_div", ctypes.c_double), ("disk_rmin", ctypes.c_double),
-                ("disk_rmax", ctypes.c_double), ("max_steps", ctypes.c_int32),
+                ("disk_rmax", ctypes.c_double), ("fp64_horizon", ctypes.c_double),
+                ("fp64_pole", ctypes.c_double), ("fp64_turn", ctypes.c_double),
+                ("max_steps", ctypes.c_int32),
                 ("call_steps", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
 
@@ -149,7 +151,8 @@ def camera_array(cams: Sequence[Camera]):
 
 def params_struct(p: Params) -> gray_params:
     return gray_params(p.step_frac, p.horizon_eps, p.r_escape, p.xi_eps, p.euler_div, p.disk_rmin,
-                       p.disk_rmax, p.max_steps, p.call_steps, PRECISIONS[p.precision],
+                       p.disk_rmax, p.fp64_horizon, p.fp64_pole, p.fp64_turn, p.max_steps,
+                       p.call_steps, PRECISIONS[p.precision],
                        GRAY_RECORD_DISK if p.record_disk else 0)
 
 

@@ -55,6 +55,12 @@ class Params:
     call_steps: int = 0
     precision: str = "fp64"      # "fp64" or "fp32c"
     record_disk: bool = False
+    # FP32C: double-precision steps near the horizon, the poles and radial
+    # turning points (r < r_bh (1 + fp64_horizon), sin(theta) < fp64_pole,
+    # |k^r| < fp64_turn |k^t|).
+    fp64_horizon: float = 1.0
+    fp64_pole: float = 0.05
+    fp64_turn: float = 0.01
 
 
 def deg(x: float) -> float:

@@ -79,7 +79,7 @@ CAM = W.Camera(0.5, 1000.0, 1.0, 8, 8, -5.0, 5.0, -5.0, 5.0)
 @pytest.mark.parametrize("field,value", [
     ("step_frac", 0.0), ("step_frac", math.inf), ("horizon_eps", 0.0), ("r_escape", -1.0),
     ("xi_eps", 0.0), ("euler_div", 0.5), ("max_steps", 0), ("call_steps", -1), ("precision", 5),
-    ("flags", 8)])
+    ("flags", 8), ("fp64_horizon", -1.0), ("fp64_pole", math.nan), ("fp64_turn", math.inf)])
 def test_invalid_params_rejected(lib, field, value):
     p = G.params_struct(W.Params())
     setattr(p, field, value)

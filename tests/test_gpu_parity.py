@@ -1,81 +1,94 @@
-"""GPU parity: libgray (through its C ABI) against the FP64 CPU oracle.
+"""GPU parity: libgray (through its C ABI) against the FP64 CPU oracle, for
+both precisions (FP64 and the compensated FP32 path, FP32C).
 
 Workloads are the seeded synthetic image-plane grids of the workload
 specification at sizes the oracle finishes in seconds, plus the full-size
 edge-on Kerr grid with the oracle on a deterministic sample of its rays.
-See tests/parity.py for the comparison rules.
+See tests/parity.py for the comparison rules and tolerances.
 """
 import numpy as np
 import pytest
 
 import analytic
 import oracle
-from parity import compare, run_gpu, run_oracle
+from parity import compare_prec, run_gpu, run_oracle
 from paper_1303_5057_amd import gray as G
 from paper_1303_5057_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-RTOL64 = 1e-5
+PRECS = ["fp64", "fp32c"]
+STEP_MISMATCH = {"fp64": 1e-3, "fp32c": 2e-3}
 
 
-def _check(rep, allow_step_mismatch=1e-3):
-    print(rep, flush=True)
+def _check(rep, prec, allow=None):
+    print(prec, rep, flush=True)
     assert rep.flag_mismatch == 0
     assert rep.state_bad == 0
     assert rep.counter_bad == 0
-    assert rep.step_mismatch <= allow_step_mismatch * rep.n
+    assert rep.step_mismatch <= (STEP_MISMATCH[prec] if allow is None else allow) * rep.n
 
 
-def test_c1_schwarzschild_full_grid_fp64():
-    cam, p = W.C1, W.Params()
+@pytest.mark.parametrize("prec", PRECS)
+def test_c1_schwarzschild_full_grid(prec):
+    cam, p = W.C1, W.Params(precision=prec)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
-    _check(compare(g.status, g.steps, g.x.T, g.counters, o, RTOL64))
+    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec), prec)
     assert np.array_equal(g.flag, g.status)
     # independent of the oracle: the sqrt(27) shadow on the pixel grid
     al, be = np.meshgrid(-10 + 20 * (np.arange(64) + 0.5) / 64, -10 + 20 * (np.arange(64) + 0.5) / 64)
     captured = (np.hypot(al, be) < analytic.SQRT27).ravel()
     assert np.array_equal(g.status == G.CAPTURED, captured)
     assert g.counts.tolist() == [np.bincount(g.status, minlength=5).tolist()]
+    if prec == "fp64":
+        assert g.counters[2].sum() == 0
+    else:
+        assert 0 < g.counters[2].sum() < g.steps.sum()
 
 
-def test_c2_kerr_ragged_grid_fp64():
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_kerr_ragged_grid(prec):
     """a = 0.99 edge-on window at 97 x 95: many 64-photon chunks plus a ragged tail."""
-    cam, p = W.scaled(W.C2, 97, 95), W.Params()
+    cam, p = W.scaled(W.C2, 97, 95), W.Params(precision=prec)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
-    _check(compare(g.status, g.steps, g.x.T, g.counters, o, RTOL64))
+    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec), prec)
     assert set(np.unique(g.status)) == {G.CAPTURED, G.ESCAPED}
 
 
-def test_c2_full_size_sampled_fp64():
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_full_size_sampled(prec):
     """Full 512 x 512 launch (as timed by the benchmark); the oracle traces every
     8th row and column."""
-    cam, p = W.C2, W.Params()
+    cam, p = W.C2, W.Params(precision=prec)
     g = run_gpu([cam], p)
     ids = W.subsample_ids(cam, 8)
     o = run_oracle(cam, p, ids)
-    _check(compare(g.status[ids], g.steps[ids], g.x.T[ids], g.counters[:, ids], o, RTOL64))
+    _check(compare_prec(g.status[ids], g.steps[ids], g.x.T[ids], g.counters[:, ids], o, prec), prec)
     assert np.all((g.status == G.CAPTURED) | (g.status == G.ESCAPED))
 
 
-def test_many_cameras_one_launch_fp64():
+@pytest.mark.parametrize("prec", PRECS)
+def test_many_cameras_one_launch(prec):
     """Seeded sweep cameras (spin, inclination, size) packed into one launch;
     each camera's slice matches the oracle run of that camera alone."""
     cams = W.sweep_cameras(count=7, side_lo=9, side_hi=40)
-    p = W.Params()
+    p = W.Params(precision=prec)
     g = run_gpu(cams, p)
     for k, cam in enumerate(cams):
         sl = slice(g.offsets[k], g.offsets[k + 1])
         o = run_oracle(cam, p)
-        _check(compare(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, RTOL64))
+        _check(compare_prec(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, prec), prec,
+               allow=0.01)
         assert g.counts[k].tolist() == np.bincount(g.status[sl], minlength=5).tolist()
 
 
-def test_resume_is_bitwise_fp64():
-    """Repeated calls of call_steps steps reproduce a single call exactly."""
-    cam, p = W.scaled(W.C2, 40, 37), W.Params()
+@pytest.mark.parametrize("prec", PRECS)
+def test_resume_is_bitwise(prec):
+    """Repeated calls of call_steps steps reproduce a single call exactly: a
+    step is a function of the stored state alone, in both precisions."""
+    cam, p = W.scaled(W.C2, 40, 37), W.Params(precision=prec)
     one = run_gpu([cam], p)
     many = run_gpu([cam], p, call_steps=37)
     assert np.array_equal(one.status, many.status)
@@ -84,19 +97,19 @@ def test_resume_is_bitwise_fp64():
     assert np.array_equal(one.x, many.x)
 
 
-def test_unfinished_and_nonfinite_fp64():
+@pytest.mark.parametrize("prec", PRECS)
+def test_unfinished_and_nonfinite(prec):
     import torch
     cam = W.scaled(W.C2, 16)
-    p = W.Params(max_steps=50)
-    g = run_gpu([cam], p)
+    g = run_gpu([cam], W.Params(max_steps=50, precision=prec))
     assert np.all(g.status == G.UNFINISHED) and np.all(g.steps == 50)
-    b = G.Batch([cam], W.Params())
+    b = G.Batch([cam], W.Params(precision=prec))
     b.camera_init()
     x = b.x.view(8, b.stride)
     x[1, 3] = float("nan")
     x[5, 100] = float("inf")
     x[6, 200] = float("nan")
-    g = run_gpu([cam], W.Params(), batch=b, init=False)
+    g = run_gpu([cam], W.Params(precision=prec), batch=b, init=False)
     bad = [3, 100, 200]
     assert np.all(g.status[bad] == G.NONFINITE)
     ok = np.setdiff1d(np.arange(cam.n), bad)
@@ -104,54 +117,65 @@ def test_unfinished_and_nonfinite_fp64():
     torch.cuda.synchronize()
 
 
-def test_pole_case_and_axis_ray_fp64():
-    p = W.Params()
+@pytest.mark.parametrize("prec", PRECS)
+def test_pole_case_and_axis_ray(prec):
+    p = W.Params(precision=prec)
     cams = [W.pole_camera(np.radians(d)) for d in (0.0, 123.0)]
     cams.append(W.Camera(0.5, 1000.0, 0.0, 1, 1, 0.0, 0.0, 0.0, 0.0))   # exactly on the axis
     g = run_gpu(cams, p)
     for k in range(2):
         o = run_oracle(cams[k], p)
         assert g.status[k] == G.CAPTURED and g.counters[1, k] >= 2
-        assert g.steps[k] == o.steps[0] and g.counters[0, k] == o.n_euler[0]
+        if prec == "fp64":
+            assert g.steps[k] == o.steps[0] and g.counters[0, k] == o.n_euler[0]
     assert g.status[2] == G.NONFINITE and g.steps[2] == 1
 
 
-def test_single_photon_and_odd_shapes_fp64():
-    p = W.Params()
+@pytest.mark.parametrize("prec", PRECS)
+def test_single_photon_and_odd_shapes(prec):
+    p = W.Params(precision=prec)
     cams = [W.scaled(W.C1, 1, 1), W.scaled(W.C2, 3, 1), W.scaled(W.C2, 1, 5), W.scaled(W.C1, 65, 1)]
     g = run_gpu(cams, p)
     for k, cam in enumerate(cams):
         sl = slice(g.offsets[k], g.offsets[k + 1])
         o = run_oracle(cam, p)
-        _check(compare(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, RTOL64), 0)
+        _check(compare_prec(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, prec), prec, 0)
 
 
-def test_classify_conserved_quantities_fp64():
-    cam, p = W.scaled(W.C2, 48), W.Params()
+@pytest.mark.parametrize("prec", PRECS)
+def test_classify_conserved_quantities_and_drift(prec):
+    """E, L_z, Q at the camera match the oracle; final E, L, Q match the
+    oracle's constants of the oracle's final state; rays that never fell back
+    to Euler keep E, L_z and Q within 1e-5 (escaped: at the end; captured: at
+    the last state with r >= 2 r_bh)."""
+    cam, p = W.scaled(W.C2, 48), W.Params(precision=prec)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
     c = g.cons
     assert np.allclose(c[0:3].T, o.cons0, rtol=1e-12, atol=1e-12)
-    same = g.steps == o.steps
+    same = (g.steps == o.steps) & (o.band_dist > 1e-2)
     cf = np.array([oracle.conserved(cam.a, x) for x in o.x])
-    assert np.allclose(c[3:6].T[same], cf[same], rtol=1e-6, atol=1e-9)
-    esc = (g.status == G.ESCAPED) & (o.band_dist > 1e-3)
-    assert np.max(c[6:9, esc]) <= 1e-5
-    cap = g.status == G.CAPTURED
-    assert np.max(c[6:9, cap]) <= 1e-5     # measured at the last state with r >= 2 r_bh
+    tol = 1e-6 if prec == "fp64" else 1e-4
+    assert np.allclose(c[3:6].T[same], cf[same], rtol=tol, atol=tol)
+    clean = (g.counters[0] == 0) & (o.band_dist > 1e-3)
+    assert clean.mean() > 0.9
+    assert np.max(c[6:9, clean & (g.status == G.ESCAPED)]) <= 1e-5
+    assert np.max(c[6:9, clean & (g.status == G.CAPTURED)]) <= 1e-5
 
 
-def test_disk_recorder_fp64():
+@pytest.mark.parametrize("prec", PRECS)
+def test_disk_recorder(prec):
     """Equatorial-crossing recorder on the a = 0.9375, i = 17 deg window."""
     cam = W.scaled(W.C3, 48)
-    p = W.Params(record_disk=True, disk_rmin=-1.0, disk_rmax=50.0)
+    p = W.Params(record_disk=True, disk_rmin=-1.0, disk_rmax=50.0, precision=prec)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
     same = (g.steps == o.steps) & (g.status == o.status)
-    assert same.mean() > 0.999
+    assert same.mean() > 0.99
     hit_g, hit_o = g.disk[0] > 0, o.disk[:, 0] > 0
     assert np.array_equal(hit_g[same], hit_o[same])
     assert hit_g.sum() > 0.3 * cam.n
     m = same & hit_o
-    assert np.allclose(g.disk.T[m], o.disk[m], rtol=1e-9, atol=1e-9)
+    tol = 1e-9 if prec == "fp64" else 1e-3
+    assert np.allclose(g.disk.T[m], o.disk[m], rtol=tol, atol=tol)
     assert np.all(g.disk[0, hit_g] >= oracle.r_isco(cam.a)) and np.all(g.disk[0, hit_g] <= 50.0)
