@@ -42,7 +42,59 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1,
                     help="oracle traces every k-th row and column of the grid")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=1100)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-precision", choices=["fp64", "fp32c"], default="fp32c")
     return ap.parse_args()
+
+
+def serving(args) -> dict:
+    """Continuous batching of camera requests (side log-uniform in [32, 2048],
+    spin U[0, 0.998], inclination U[0, 90] deg, Poisson arrivals): saturation
+    throughput from a closed loop, then p50/p99 latency at 0.5x and 0.9x of
+    the saturation request rate; the first serve-warmup requests are not
+    counted."""
+    import numpy as np
+    from paper_1303_5057_amd import workloads as W
+    from paper_1303_5057_amd.serve import Server, latency_stats
+
+    budget = int(args.serve_budget_gb * (1 << 30))
+    params = W.Params(precision=args.serve_precision)
+    n = args.serve_requests
+    def progress(tag):
+        last = [time.perf_counter()]
+
+        def cb(r):
+            now = time.perf_counter()
+            if now - last[0] > 5.0:
+                print(f"bench: serving {tag}: request {r.rid} done", file=sys.stderr, flush=True)
+                last[0] = now
+        return cb
+
+    closed = [W.Request(r.rid, 0.0, r.camera) for r in W.request_stream(n, qps=1.0)]
+    srv = Server(budget, params)
+    t0 = time.perf_counter()
+    res = srv.run(closed, realtime=False, on_done=progress("closed loop"))
+    wall = time.perf_counter() - t0
+    qps_sat = len(res) / wall
+    out = {"precision": args.serve_precision, "budget_gb": args.serve_budget_gb,
+           "pool_photons": srv.capacity, "requests": n, "warmup": args.serve_warmup,
+           "saturation": {"requests_per_s": qps_sat,
+                          "photon_steps_per_s": sum(r.photon_steps for r in res) / wall,
+                          "mean_photons_per_request": float(np.mean([r.photons for r in res])),
+                          "max_in_flight": srv.max_active}}
+    for frac in (0.5, 0.9):
+        reqs = W.request_stream(n, qps=frac * qps_sat)
+        srv = Server(budget, params)
+        res = srv.run(reqs, realtime=True, on_done=progress(f"{frac}x load"))
+        st = latency_stats(res, skip=args.serve_warmup)
+        out[f"load_{frac}"] = {"qps": frac * qps_sat, "p50_ms": st["p50_ms"],
+                               "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                               "photon_steps_per_s": st["photon_steps_per_s"],
+                               "max_in_flight": srv.max_active, "iterations": srv.iterations}
+    return out
 
 
 def cpu_baseline(cam, params, every: int):
@@ -133,6 +185,7 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 3
     cam = W.C2
+    print("bench: timing the 512x512 workload", file=sys.stderr, flush=True)
     head = measure(G, W, torch, np, cam, args.precision, args.steps, args.warmup)
     other_prec = "fp32c" if args.precision == "fp64" else "fp64"
     other = measure(G, W, torch, np, cam, other_prec, args.steps, args.warmup)
@@ -176,7 +229,11 @@ def main():
                      "status_counts": other["status"], "drift_ELQ": other["drift"]},
         "fp32c_speedup_vs_fp64": t64 / t32,
     }
+    if not args.no_serve:
+        print("bench: serving", file=sys.stderr, flush=True)
+        out["serving"] = serving(args)
     if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cam, head["params"], args.cpu_sample)
     print(json.dumps(out), flush=True)
     return 0

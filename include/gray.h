@@ -46,6 +46,19 @@
  *          inside the recorder window (r_c, phi_c, redshift g); all zero
  *          when there was none. Required when GRAY_RECORD_DISK is set.
  *   stride must be >= n and a multiple of 64; all rows are stride apart.
+ *   work_in, work_out, work_in_count, work_out_count
+ *          work-list mode only (GRAY_WORKLIST), else NULL: int32 photon-id
+ *          lists of capacity n + GRAY_WORKLIST_SLACK each, and their uint32
+ *          lengths, all device memory. gray_integrate advances the photons listed in
+ *          work_in[0 .. *work_in_count) and appends to work_out the ids that
+ *          are still GRAY_RUNNING when it stops (it zeroes *work_out_count
+ *          first; the order of ids is unspecified, and entries equal to -1 are
+ *          unused space that readers skip). gray_camera_init_slot
+ *          appends the new slot's ids to work_in. A caller that iterates swaps
+ *          (work_in, work_in_count) with (work_out, work_out_count) between
+ *          integrate calls, so each call's work is the live photons only.
+ *          gray_classify in this mode classifies only the photons listed in
+ *          work_in (flag and counts; xf and cons must be NULL).
  */
 #ifndef GRAY_H
 #define GRAY_H
@@ -81,6 +94,17 @@ typedef enum {
 
 /* gray_params.flags */
 #define GRAY_RECORD_DISK 1u /* record the first equatorial crossing (Sec. 3) */
+#define GRAY_WORKLIST 4u    /* work-list mode, see gray_state                */
+#define GRAY_WORKLIST_SLACK (1 << 20) /* extra list entries a call may leave unused */
+#define GRAY_SLOTS 2u       /* slot mode, for callers that keep many requests in
+                               one resident photon pool (continuous batching):
+                               `cams` is a slot table and camera k covers photon
+                               ids [first, first + nx * ny) in any order; ranges
+                               are disjoint and inside [0, n); nx * ny == 0
+                               marks a free slot. The camera index stored per
+                               photon is the slot index. Photons outside every
+                               camera are ignored by camera_init and classify
+                               and must not be GRAY_RUNNING for integrate.   */
 
 /* One camera: a Kerr hole of spin a seen from distance r_obs at inclination
  * incl (radians from the spin axis, azimuth 0), with a regular cell-centred
@@ -91,7 +115,8 @@ typedef enum {
  *           spin axis)
  * and is photon  first + iy * nx + ix.  Constraints: 0 <= a < 1,
  * r_obs > r_bh = 1 + sqrt(1 - a^2), 0 <= incl <= pi, nx, ny >= 1, finite
- * ranges. Cameras passed together must tile [0, n) in order with no gaps. */
+ * ranges. Cameras passed together must tile [0, n) in order with no gaps
+ * (unless GRAY_SLOTS is set). */
 typedef struct {
     double a, r_obs, incl;
     int32_t nx, ny;
@@ -133,6 +158,14 @@ typedef struct {
     double *disk;
     int64_t n;
     int64_t stride;
+    int32_t *work_in;
+    int32_t *work_out;
+    uint32_t *work_in_count;
+    uint32_t *work_out_count;
+    uint32_t *cam_done;   /* optional [ncam]: photons of each camera that have
+                             stopped in a terminal status; camera_init (and
+                             camera_init_slot for its slot) zeroes the entry,
+                             gray_integrate adds to it as photons stop       */
 } gray_state;
 
 /* Outputs of gray_classify, all device memory, all rows `stride` apart
@@ -159,6 +192,14 @@ size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params *p);
  * clears counters, mark and disk when present. */
 int gray_camera_init(const gray_camera *cams, int32_t ncam, const gray_params *p,
                      gray_state *s, void *hip_stream);
+
+/* Slot mode (GRAY_SLOTS must be set in p->flags): initialise only the photons
+ * of cams[slot] (ids [first, first + nx * ny)), storing `slot` as their camera
+ * index; the rest of the state is untouched. Same layout and ownership rules
+ * as gray_camera_init. Returns GRAY_EINVAL when slot is outside [0, ncam), the
+ * slot is empty, or the slot table is invalid. */
+int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int32_t slot,
+                          const gray_params *p, gray_state *s, void *hip_stream);
 
 /* Integrate every GRAY_RUNNING photon with the scheme of Sec. 2 until it is
  * captured, escapes, turns non-finite or reaches max_steps (or until it has

@@ -17,8 +17,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
+#include <utility>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -44,7 +48,11 @@ static int check_launch(const char *what)
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kCamChunk = 16;          // cameras per by-value kernel argument
-constexpr unsigned kQueueChunk = 64;   // photons per queue grab (one per lane)
+constexpr unsigned kQueueChunk = 64;   // photons per refill round (one per lane)
+constexpr unsigned kMaxGrab = 8;       // refill rounds per queue grab, at most
+constexpr unsigned kSpan = 512;        // work-list ids reserved per append grab
+constexpr int64_t kMaxListWaves = 2048; // waves of a work-list launch, at most
+static_assert(kMaxListWaves * kSpan <= GRAY_WORKLIST_SLACK, "list slack covers every wave's last span");
 constexpr size_t kWsHeader = 256;      // queue counter, padded
 constexpr int64_t kMaxPhotons = (int64_t)1 << 31;
 
@@ -63,7 +71,7 @@ struct CamArg {
 struct CamChunk {
     CamArg c[kCamChunk];
     int32_t count;
-    int32_t pad;
+    int32_t sparse;   // slot mode: photons in [lo, hi) may belong to no camera here
     int64_t lo, hi;   // photon range [lo, hi) covered by these cameras
 };
 struct SetupChunk {
@@ -78,8 +86,14 @@ __device__ __forceinline__ unsigned lane_rank(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// Camera of photon i within a chunk, or -1 (slot mode only) when none covers it.
 __device__ __forceinline__ int find_camera(const CamChunk &ch, int64_t i)
 {
+    if (ch.sparse) {
+        for (int j = 0; j < ch.count; ++j)
+            if (i >= ch.c[j].first && i < ch.c[j].first + (int64_t)ch.c[j].nx * ch.c[j].ny) return j;
+        return -1;
+    }
     int k = 0;
     for (int j = 1; j < ch.count; ++j)
         if (i >= ch.c[j].first) k = j;
@@ -100,6 +114,9 @@ struct InitArgs {
     void *x, *lo;
     int32_t *status, *steps, *cam, *counters;
     double *mark, *disk;
+    int32_t *work;          // work-list mode: append initialised ids here
+    unsigned *work_count;
+    unsigned *cam_done;     // zeroed for the cameras of the chunk
     int64_t stride;
     int32_t precision, pad;
     CamChunk ch;
@@ -107,9 +124,13 @@ struct InitArgs {
 
 __global__ __launch_bounds__(kBlock) void k_camera_init(InitArgs A)
 {
+    if (A.cam_done && blockIdx.x == 0 && threadIdx.x < (unsigned)A.ch.count)
+        A.cam_done[A.ch.c[threadIdx.x].index] = 0u;
     const int64_t i = A.ch.lo + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= A.ch.hi) return;
-    const CamArg &c = A.ch.c[find_camera(A.ch, i)];
+    const int kc = find_camera(A.ch, i);
+    if (kc < 0) return;
+    const CamArg &c = A.ch.c[kc];
     double alpha, beta;
     pixel_of(c, i, alpha, beta);
     State<double> x;
@@ -135,14 +156,25 @@ __global__ __launch_bounds__(kBlock) void k_camera_init(InitArgs A)
     if (A.mark) A.mark[1 * S + i] = 0.0;
     if (A.disk)
         for (int k = 0; k < 3; ++k) A.disk[k * S + i] = 0.0;
+    if (A.work) {
+        const uint64_t m = ballot(true);
+        const unsigned lane = threadIdx.x & (kWave - 1);
+        unsigned base = 0;
+        if (lane == (unsigned)(__ffsll((long long)m) - 1)) base = atomicAdd(A.work_count, (unsigned)__popcll(m));
+        base = __builtin_amdgcn_readfirstlane(base);
+        A.work[base + lane_rank(m)] = (int32_t)i;
+    }
 }
 
 // ------------------------------------------------------------ workspace setup
-__global__ void k_setup(DevCam *table, unsigned *queue, SetupChunk ch)
+__global__ void k_setup(DevCam *table, unsigned *queue, unsigned *work_out_count, SetupChunk ch)
 {
     const int j = threadIdx.x;
     if (j < ch.count) table[ch.base + j] = ch.c[j];
-    if (ch.base == 0 && j == 0) *queue = 0u;
+    if (ch.base == 0 && j == 0) {
+        *queue = 0u;
+        if (work_out_count) *work_out_count = 0u;
+    }
 }
 
 
@@ -155,6 +187,11 @@ struct IntArgs {
     double *mark, *disk;
     const DevCam *cams;
     unsigned *queue;
+    const int32_t *work_in;     // work-list mode: ids to advance, count at *work_in_count
+    int32_t *work_out;          // ids still running at the end, count at *work_out_count
+    const unsigned *work_in_count;
+    unsigned *work_out_count;
+    unsigned *cam_done;         // per-camera count of photons that stopped
     int64_t n, stride;
     double step_frac, xi_eps, euler_div, r_escape;
     double fp64_horizon, fp64_pole, fp64_turn;
@@ -263,24 +300,36 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 
     unsigned chunk_next = 0, chunk_end = 0;
     bool exhausted = false;
+    // Queue length: all photon ids, or the length of the work list.
+    const int64_t nq = A.work_in ? (int64_t)__builtin_amdgcn_readfirstlane(*A.work_in_count) : A.n;
+    // A grab takes `grab` ids (a multiple of 64): large enough to keep the
+    // single queue counter off the critical path, small enough that every wave
+    // gets about four grabs.
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    int64_t rounds = nq / (waves * kQueueChunk * 4);
+    rounds = rounds < 1 ? 1 : (rounds > kMaxGrab ? kMaxGrab : rounds);
+    const unsigned grab = (unsigned)rounds * kQueueChunk;
+    // Work-list output: a private span of kSpan reserved slots per wave.
+    unsigned span_next = 0, span_end = 0;
 
     for (;;) {
         const uint64_t idle = ballot(!active);
         if (__popcll(idle) >= A.refill || idle == ~0ull) {
             if (chunk_next >= chunk_end && !exhausted) {
                 unsigned base = 0;
-                if (lane == 0) base = atomicAdd(A.queue, kQueueChunk);
+                if (lane == 0) base = atomicAdd(A.queue, grab);
                 base = __builtin_amdgcn_readfirstlane(base);
-                if ((int64_t)base + kQueueChunk >= A.n) exhausted = true;
-                chunk_next = (int64_t)base < A.n ? base : (unsigned)A.n;
-                chunk_end = (int64_t)base + kQueueChunk < A.n ? base + kQueueChunk : (unsigned)A.n;
+                if ((int64_t)base + grab >= nq) exhausted = true;
+                chunk_next = (int64_t)base < nq ? base : (unsigned)nq;
+                chunk_end = (int64_t)base + grab < nq ? base + grab : (unsigned)nq;
             }
             const unsigned avail = chunk_end - chunk_next;
             if (avail > 0) {
                 const unsigned rank = lane_rank(idle);
                 if (!active && rank < avail) {
-                    id = (int64_t)(chunk_next + rank);
-                    if (A.status[id] == GRAY_RUNNING) {
+                    const unsigned q = chunk_next + rank;
+                    id = A.work_in ? (int64_t)A.work_in[q] : (int64_t)q;
+                    if (id >= 0 && A.status[id] == GRAY_RUNNING) {
                         L.load(A, id);
                         const DevCam cm = A.cams[A.cam[id]];
                         K.B = make_spin(cm.a);
@@ -312,9 +361,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 const unsigned taken = __popcll(idle) < avail ? (unsigned)__popcll(idle) : avail;
                 chunk_next += taken;
             }
-            if (exhausted && chunk_next >= chunk_end && ballot(active) == 0ull) break;
+            if (exhausted && chunk_next >= chunk_end && ballot(active) == 0ull) {
+                // mark the unused rest of this wave's output span
+                if (A.work_out)
+                    for (unsigned j = span_next + lane; j < span_end; j += kWave) A.work_out[j] = -1;
+                break;
+            }
         }
 
+        bool stop_now = false, keep = false;
         if (active) {
             const State<double> xp = L.value();
             State<double> x;
@@ -384,7 +439,51 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                     A.counters[1 * S + id] = nr;
                     A.counters[2 * S + id] = n64;
                 }
+                stop_now = true;
+                keep = st == GRAY_RUNNING;
                 active = false;
+            }
+        }
+
+        // Wave-uniform bookkeeping of the photons that stopped this iteration.
+        if (A.work_out) {
+            // Photons still running go on the next work list, written into
+            // the wave's reserved span; when it fills up the rest continues
+            // in a fresh span of kSpan slots, so the only unused slots are
+            // the tail of each wave's last span (marked -1 at exit).
+            const uint64_t m = ballot(keep);
+            const unsigned cnt = (unsigned)__popcll(m);
+            if (cnt) {
+                const unsigned room = span_end - span_next;
+                unsigned fresh = 0;
+                if (cnt > room) {
+                    if (lane == 0) fresh = atomicAdd(A.work_out_count, kSpan);
+                    fresh = __builtin_amdgcn_readfirstlane(fresh);
+                }
+                const unsigned r = lane_rank(m);
+                if (keep) A.work_out[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
+                if (cnt > room) {
+                    span_next = fresh + (cnt - room);
+                    span_end = fresh + kSpan;
+                } else {
+                    span_next += cnt;
+                }
+            }
+        }
+        if (A.cam_done) {
+            // Completion count per camera: one atomic per wave when the
+            // photons that finished share a camera.
+            const bool fin = stop_now && !keep;
+            const uint64_t mf = ballot(fin);
+            if (mf) {
+                const int32_t c = fin ? A.cam[id] : -1;
+                const unsigned lead = (unsigned)(__ffsll((long long)mf) - 1);
+                const int32_t cl = __shfl(c, (int)lead, kWave);
+                if (ballot(fin && c != cl) == 0ull) {
+                    if (lane == lead) atomicAdd(&A.cam_done[cl], (unsigned)__popcll(mf));
+                } else if (fin) {
+                    atomicAdd(&A.cam_done[c], 1u);
+                }
             }
         }
     }
@@ -409,11 +508,43 @@ __global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *p, int64_t n)
     if (i < n) p[i] = 0;
 }
 
+// Work-list classification: flags and per-camera status counts of the listed
+// photons only (grid-stride over a list whose length is on the device).
+__global__ __launch_bounds__(kBlock) void k_classify_list(const int32_t *list, const unsigned *count,
+                                                          const int32_t *status, const int32_t *cam,
+                                                          int8_t *flag, int32_t *counts, int32_t ncam)
+{
+    const int64_t n = (int64_t)__builtin_amdgcn_readfirstlane(*count);
+    const unsigned lane = threadIdx.x & (kWave - 1);
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = list[j];
+        if (i < 0) continue;
+        const int32_t st = status[i];
+        flag[i] = (int8_t)st;
+        if (!counts) continue;
+        const int sb = (st >= 0 && st < 5) ? st : 4;
+        const int32_t c = cam[i];
+        const int32_t c0 = __builtin_amdgcn_readfirstlane(c);
+        if (ballot(c != c0) == 0ull) {
+            if (c0 < 0 || c0 >= ncam) continue;
+            const uint64_t act = ballot(true);
+            for (int k = 0; k < 5; ++k) {
+                const uint64_t m = ballot(sb == k);
+                if (m && lane == (unsigned)(__ffsll((long long)act) - 1))
+                    atomicAdd(&counts[c0 * 5 + k], (int)__popcll(m));
+            }
+        } else if (c >= 0 && c < ncam) {
+            atomicAdd(&counts[c * 5 + sb], 1);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_classify(ClassArgs A)
 {
     const int64_t i = A.ch.lo + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= A.ch.hi) return;
     const int k = find_camera(A.ch, i);
+    if (k < 0) return;
     const CamArg &c = A.ch.c[k];
     const int64_t S = A.stride;
     const int32_t st = A.status[i];
@@ -490,7 +621,7 @@ static int validate_params(const gray_params *p)
     if (!(p->euler_div >= 1.0 && std::isfinite(p->euler_div))) return GRAY_EINVAL;
     if (p->max_steps < 1 || p->call_steps < 0) return GRAY_EINVAL;
     if (p->precision != GRAY_FP64 && p->precision != GRAY_FP32C) return GRAY_EINVAL;
-    if (p->flags & ~GRAY_RECORD_DISK) return GRAY_EINVAL;
+    if (p->flags & ~(GRAY_RECORD_DISK | GRAY_SLOTS | GRAY_WORKLIST)) return GRAY_EINVAL;
     if (!(p->fp64_horizon >= 0.0 && std::isfinite(p->fp64_horizon))) return GRAY_EINVAL;
     if (!(p->fp64_pole >= 0.0 && std::isfinite(p->fp64_pole))) return GRAY_EINVAL;
     if (!(p->fp64_turn >= 0.0 && std::isfinite(p->fp64_turn))) return GRAY_EINVAL;
@@ -500,19 +631,42 @@ static int validate_params(const gray_params *p)
     return GRAY_OK;
 }
 
-static int validate_cameras(const gray_camera *cams, int32_t ncam, int64_t n)
+static bool camera_physical_ok(const gray_camera &c)
+{
+    if (!(c.a >= 0.0 && c.a < 1.0)) return false;
+    if (!(c.r_obs > horizon_radius(c.a) && std::isfinite(c.r_obs))) return false;
+    if (!(c.incl >= 0.0 && c.incl <= kPi)) return false;
+    return std::isfinite(c.alpha_lo) && std::isfinite(c.alpha_hi) && std::isfinite(c.beta_lo) &&
+           std::isfinite(c.beta_hi);
+}
+
+// Dense mode: cameras tile [0, n) in order. Slot mode: disjoint ranges inside
+// [0, n) in any order, empty slots allowed.
+static int validate_cameras(const gray_camera *cams, int32_t ncam, int64_t n, uint32_t flags)
 {
     if (!cams || ncam < 1) return GRAY_EINVAL;
+    if (flags & GRAY_SLOTS) {
+        std::vector<std::pair<int64_t, int64_t>> r;
+        r.reserve(ncam);
+        for (int32_t k = 0; k < ncam; ++k) {
+            const gray_camera &c = cams[k];
+            if (c.nx < 0 || c.ny < 0) return GRAY_EINVAL;
+            const int64_t m = (int64_t)c.nx * c.ny;
+            if (m == 0) continue;
+            if (!camera_physical_ok(c)) return GRAY_EINVAL;
+            if (c.first < 0 || c.first + m > n) return GRAY_EINVAL;
+            r.emplace_back(c.first, c.first + m);
+        }
+        std::sort(r.begin(), r.end());
+        for (size_t k = 1; k < r.size(); ++k)
+            if (r[k].first < r[k - 1].second) return GRAY_EINVAL;
+        return GRAY_OK;
+    }
     int64_t next = 0;
     for (int32_t k = 0; k < ncam; ++k) {
         const gray_camera &c = cams[k];
-        if (!(c.a >= 0.0 && c.a < 1.0)) return GRAY_EINVAL;
-        if (!(c.r_obs > horizon_radius(c.a) && std::isfinite(c.r_obs))) return GRAY_EINVAL;
-        if (!(c.incl >= 0.0 && c.incl <= kPi)) return GRAY_EINVAL;
+        if (!camera_physical_ok(c)) return GRAY_EINVAL;
         if (c.nx < 1 || c.ny < 1) return GRAY_EINVAL;
-        if (!(std::isfinite(c.alpha_lo) && std::isfinite(c.alpha_hi) && std::isfinite(c.beta_lo) &&
-              std::isfinite(c.beta_hi)))
-            return GRAY_EINVAL;
         if (c.first != next) return GRAY_EINVAL;
         next += (int64_t)c.nx * c.ny;
         if (next > n) return GRAY_EINVAL;
@@ -523,23 +677,31 @@ static int validate_cameras(const gray_camera *cams, int32_t ncam, int64_t n)
 static int validate_state(const gray_state *s, const gray_params *p)
 {
     if (!s) return GRAY_EINVAL;
-    if (s->n < 0 || s->n >= kMaxPhotons - (int64_t)kQueueChunk) return GRAY_EINVAL;
+    if (s->n < 0 || s->n >= kMaxPhotons - (int64_t)(kQueueChunk * kMaxGrab + kSpan)) return GRAY_EINVAL;
     if (s->n == 0) return GRAY_OK;
     if (s->stride < s->n || s->stride % kWave != 0) return GRAY_EINVAL;
     if (!s->x || !s->status || !s->steps || !s->cam) return GRAY_EINVAL;
     if (p->precision == GRAY_FP32C && !s->lo) return GRAY_EINVAL;
     if (p->precision == GRAY_FP64 && s->lo) return GRAY_EINVAL;
     if ((p->flags & GRAY_RECORD_DISK) && !s->disk) return GRAY_EINVAL;
+    const bool wl = (p->flags & GRAY_WORKLIST) != 0;
+    if (wl != (s->work_in && s->work_out && s->work_in_count && s->work_out_count)) return GRAY_EINVAL;
+    if (!wl && (s->work_in || s->work_out || s->work_in_count || s->work_out_count)) return GRAY_EINVAL;
     return GRAY_OK;
 }
 
-static void fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, CamChunk &ch)
+// Chunk of up to kCamChunk cameras as a kernel argument; in slot mode empty
+// slots are left out. Returns false when the chunk covers no photon.
+static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool slots, CamChunk &ch)
 {
     memset(&ch, 0, sizeof ch);
-    ch.count = cnt;
+    ch.sparse = slots ? 1 : 0;
+    int64_t lo = INT64_MAX, hi = 0;
     for (int32_t j = 0; j < cnt; ++j) {
         const gray_camera &c = cams[k0 + j];
-        CamArg &o = ch.c[j];
+        const int64_t m = (int64_t)c.nx * c.ny;
+        if (m == 0) continue;
+        CamArg &o = ch.c[ch.count++];
         o.a = c.a;
         o.r_obs = c.r_obs;
         o.incl = c.incl;
@@ -551,10 +713,12 @@ static void fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, CamChun
         o.nx = c.nx;
         o.ny = c.ny;
         o.index = k0 + j;
+        lo = std::min(lo, c.first);
+        hi = std::max(hi, c.first + m);
     }
-    ch.lo = cams[k0].first;
-    const gray_camera &last = cams[k0 + cnt - 1];
-    ch.hi = last.first + (int64_t)last.nx * last.ny;
+    ch.lo = lo;
+    ch.hi = hi;
+    return ch.count > 0;
 }
 
 struct DeviceInfo {
@@ -601,6 +765,32 @@ extern "C" size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params
     return kWsHeader + (size_t)ncam * sizeof(DevCam);
 }
 
+static int launch_init(const gray_camera *cams, int32_t k0, int32_t cnt, const gray_params *p,
+                       gray_state *s, hipStream_t st)
+{
+    InitArgs A;
+    memset(&A, 0, sizeof A);
+    A.x = s->x;
+    A.lo = s->lo;
+    A.status = s->status;
+    A.steps = s->steps;
+    A.cam = s->cam;
+    A.counters = s->counters;
+    A.mark = s->mark;
+    A.disk = s->disk;
+    if (p->flags & GRAY_WORKLIST) {
+        A.work = s->work_in;
+        A.work_count = s->work_in_count;
+    }
+    A.cam_done = s->cam_done;
+    A.stride = s->stride;
+    A.precision = p->precision;
+    if (!fill_chunk(cams, k0, cnt, (p->flags & GRAY_SLOTS) != 0, A.ch)) return GRAY_OK;
+    const int64_t m = A.ch.hi - A.ch.lo;
+    hipLaunchKernelGGL(k_camera_init, dim3(blocks_for(m)), dim3(kBlock), 0, st, A);
+    return check_launch("camera_init launch");
+}
+
 extern "C" int gray_camera_init(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
                                 void *hip_stream)
 {
@@ -608,28 +798,24 @@ extern "C" int gray_camera_init(const gray_camera *cams, int32_t ncam, const gra
     if (e) return e;
     if ((e = validate_state(s, p))) return e;
     if (s->n == 0) return GRAY_OK;
-    if ((e = validate_cameras(cams, ncam, s->n))) return e;
+    if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
     hipStream_t st = (hipStream_t)hip_stream;
-    for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
-        InitArgs A;
-        memset(&A, 0, sizeof A);
-        A.x = s->x;
-        A.lo = s->lo;
-        A.status = s->status;
-        A.steps = s->steps;
-        A.cam = s->cam;
-        A.counters = s->counters;
-        A.mark = s->mark;
-        A.disk = s->disk;
-        A.stride = s->stride;
-        A.precision = p->precision;
-        fill_chunk(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk, A.ch);
-        const int64_t cnt = A.ch.hi - A.ch.lo;
-        if (cnt <= 0) continue;
-        hipLaunchKernelGGL(k_camera_init, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, A);
-        if ((e = check_launch("camera_init launch"))) return e;
-    }
+    for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk)
+        if ((e = launch_init(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk, p, s, st))) return e;
     return GRAY_OK;
+}
+
+extern "C" int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int32_t slot, const gray_params *p,
+                                     gray_state *s, void *hip_stream)
+{
+    int e = validate_params(p);
+    if (e) return e;
+    if (!(p->flags & GRAY_SLOTS)) return GRAY_EINVAL;
+    if ((e = validate_state(s, p))) return e;
+    if (s->n == 0) return GRAY_EINVAL;
+    if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
+    if (slot < 0 || slot >= ncam || (int64_t)cams[slot].nx * cams[slot].ny == 0) return GRAY_EINVAL;
+    return launch_init(cams, slot, 1, p, s, (hipStream_t)hip_stream);
 }
 
 extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
@@ -639,7 +825,7 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     if (e) return e;
     if ((e = validate_state(s, p))) return e;
     if (s->n == 0) return GRAY_OK;
-    if ((e = validate_cameras(cams, ncam, s->n))) return e;
+    if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
     if (!workspace || ((uintptr_t)workspace & 255u) != 0 ||
         workspace_bytes < gray_workspace_size(s->n, ncam, p))
         return GRAY_EWORKSPACE;
@@ -666,7 +852,8 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
             d.disk_rmin = p->disk_rmin < 0.0 ? isco_radius(c.a) : p->disk_rmin;
             d.disk_rmax = p->disk_rmax;
         }
-        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, queue, ch);
+        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, queue,
+                           (p->flags & GRAY_WORKLIST) ? s->work_out_count : (unsigned *)nullptr, ch);
         if ((e = check_launch("setup launch"))) return e;
     }
 
@@ -682,6 +869,13 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.disk = s->disk;
     A.cams = table;
     A.queue = queue;
+    if (p->flags & GRAY_WORKLIST) {
+        A.work_in = s->work_in;
+        A.work_out = s->work_out;
+        A.work_in_count = s->work_in_count;
+        A.work_out_count = s->work_out_count;
+    }
+    A.cam_done = s->cam_done;
     A.n = s->n;
     A.stride = s->stride;
     A.step_frac = p->step_frac;
@@ -696,7 +890,10 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.flags = p->flags;
     A.refill = 1;
     const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[p->precision];
-    const int64_t need = blocks_for(s->n);
+    // In work-list mode the list length is only known on the device; the grid
+    // is capped at kMaxListWaves waves, which bounds the unused list tail.
+    const int64_t need = (p->flags & GRAY_WORKLIST) ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave))
+                                                    : blocks_for(s->n);
     const unsigned grid = (unsigned)(need < resident ? need : resident);
     if (p->precision == GRAY_FP64)
         hipLaunchKernelGGL(k_integrate<GRAY_FP64>, dim3(grid), dim3(kBlock), 0, st, A);
@@ -713,13 +910,23 @@ extern "C" int gray_classify(const gray_camera *cams, int32_t ncam, const gray_p
     if ((e = validate_state(s, p))) return e;
     if (!out) return GRAY_EINVAL;
     if (s->n == 0) return GRAY_OK;
-    if ((e = validate_cameras(cams, ncam, s->n))) return e;
+    if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
     if (!out->flag) return GRAY_EINVAL;
+    const bool wl = (p->flags & GRAY_WORKLIST) != 0;
+    if (wl && (out->xf || out->cons)) return GRAY_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
     if (out->counts) {
         const int64_t m = (int64_t)ncam * 5;
         hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(m)), dim3(kBlock), 0, st, out->counts, m);
         if ((e = check_launch("classify zero launch"))) return e;
+    }
+    if (wl) {
+        DeviceInfo dev;
+        if ((e = device_info(dev))) return e;
+        const int64_t grid = std::min<int64_t>((int64_t)dev.cus * 4, blocks_for(s->n));
+        hipLaunchKernelGGL(k_classify_list, dim3((unsigned)grid), dim3(kBlock), 0, st, s->work_in,
+                           s->work_in_count, s->status, s->cam, out->flag, out->counts, ncam);
+        return check_launch("classify list launch");
     }
     for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
         ClassArgs A;
@@ -734,9 +941,10 @@ extern "C" int gray_classify(const gray_camera *cams, int32_t ncam, const gray_p
         A.counts = out->counts;
         A.stride = s->stride;
         A.precision = p->precision;
-        fill_chunk(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk, A.ch);
+        if (!fill_chunk(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk,
+                        (p->flags & GRAY_SLOTS) != 0, A.ch))
+            continue;
         const int64_t cnt = A.ch.hi - A.ch.lo;
-        if (cnt <= 0) continue;
         hipLaunchKernelGGL(k_classify, dim3(blocks_for(cnt)), dim3(kBlock), 0, st, A);
         if ((e = check_launch("classify launch"))) return e;
     }

@@ -26,6 +26,9 @@ GRAY_OK, GRAY_EINVAL, GRAY_EDEVICE, GRAY_EWORKSPACE, GRAY_EUNSUPPORTED = 0, -1, 
 GRAY_FP64, GRAY_FP32C = 0, 1
 RUNNING, CAPTURED, ESCAPED, UNFINISHED, NONFINITE = range(5)
 GRAY_RECORD_DISK = 1
+GRAY_SLOTS = 2
+GRAY_WORKLIST = 4
+GRAY_WORKLIST_SLACK = 1 << 20
 PRECISIONS = {"fp64": GRAY_FP64, "fp32c": GRAY_FP32C}
 
 
@@ -52,7 +55,9 @@ class gray_state(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("status", ctypes.c_void_p),
                 ("steps", ctypes.c_void_p), ("cam", ctypes.c_void_p), ("counters", ctypes.c_void_p),
                 ("mark", ctypes.c_void_p), ("disk", ctypes.c_void_p), ("n", ctypes.c_int64),
-                ("stride", ctypes.c_int64)]
+                ("stride", ctypes.c_int64), ("work_in", ctypes.c_void_p),
+                ("work_out", ctypes.c_void_p), ("work_in_count", ctypes.c_void_p),
+                ("work_out_count", ctypes.c_void_p), ("cam_done", ctypes.c_void_p)]
 
 
 class gray_result(ctypes.Structure):
@@ -60,8 +65,8 @@ class gray_result(ctypes.Structure):
                 ("counts", ctypes.c_void_p)]
 
 
-EXPORTS = ("gray_workspace_size", "gray_camera_init", "gray_integrate", "gray_classify",
-           "gray_strerror", "gray_version", "gray_struct_size")
+EXPORTS = ("gray_workspace_size", "gray_camera_init", "gray_camera_init_slot", "gray_integrate",
+           "gray_classify", "gray_strerror", "gray_version", "gray_struct_size")
 
 
 class GrayError(RuntimeError):
@@ -86,6 +91,8 @@ def load() -> ctypes.CDLL:
     i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
     L.gray_workspace_size.restype, L.gray_workspace_size.argtypes = sz, [i64, i32, P]
     L.gray_camera_init.restype, L.gray_camera_init.argtypes = ctypes.c_int, [C, i32, P, S, vp]
+    L.gray_camera_init_slot.restype = ctypes.c_int
+    L.gray_camera_init_slot.argtypes = [C, i32, i32, P, S, vp]
     L.gray_integrate.restype, L.gray_integrate.argtypes = ctypes.c_int, [C, i32, P, S, vp, sz, vp]
     L.gray_classify.restype, L.gray_classify.argtypes = ctypes.c_int, [C, i32, P, S, R, vp]
     L.gray_strerror.restype, L.gray_strerror.argtypes = ctypes.c_char_p, [ctypes.c_int]
@@ -113,6 +120,13 @@ def gray_workspace_size(n: int, ncam: int, p: gray_params) -> int:
 def gray_camera_init(cams, ncam: int, p: gray_params, s: gray_state, stream: int = 0) -> int:
     return _check("gray_camera_init",
                   load().gray_camera_init(cams, ncam, ctypes.byref(p), ctypes.byref(s), stream))
+
+
+def gray_camera_init_slot(cams, ncam: int, slot: int, p: gray_params, s: gray_state,
+                          stream: int = 0) -> int:
+    return _check("gray_camera_init_slot",
+                  load().gray_camera_init_slot(cams, ncam, slot, ctypes.byref(p), ctypes.byref(s),
+                                               stream))
 
 
 def gray_integrate(cams, ncam: int, p: gray_params, s: gray_state, workspace: int,

@@ -1,0 +1,272 @@
+"""Continuous-batching request loop for camera requests (image renders).
+
+Requests (a camera each: spin, inclination, image size) arrive over time.
+All admitted requests share one resident photon pool in HBM and are advanced
+together by ONE persistent integrate launch per iteration (slot mode of the C
+ABI: the camera table is a slot table, one slot per in-flight request). The
+launch works through a list of live photon ids and writes the list of those
+still running (work-list mode), so an iteration costs what the live photons
+cost, not what the pool holds.
+Between iterations the loop
+
+  * retires requests whose photons have all stopped (per-slot counts of
+    stopped photons kept by the integrator, read back with one small
+    device-to-host copy),
+  * admits waiting requests in arrival order while a slot is free and their
+    photons fit the pool (admission by HBM footprint; no bypass, so large
+    requests are not starved),
+  * sizes the next iteration's step budget (call_steps) so that an iteration
+    takes about `slice_ms`.
+
+A photon's step is a function of its stored state alone, so a request's
+result does not depend on what else is in the pool or on how its steps are
+split into iterations.
+
+The loop is host code (scheduling); every step of the hot path runs in the
+HIP kernels of libgray.
+"""
+from __future__ import annotations
+
+import bisect
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import gray as G
+from .workloads import Camera, Params, Request
+
+ALIGN = 64
+
+
+class RangeAllocator:
+    """First-fit allocator of photon ranges in [0, capacity), 64-aligned."""
+
+    def __init__(self, capacity: int):
+        self.capacity = capacity
+        self.free: List[List[int]] = [[0, capacity]]   # sorted [start, end)
+
+    def alloc(self, n: int) -> Optional[int]:
+        need = (n + ALIGN - 1) // ALIGN * ALIGN
+        for k, (s, e) in enumerate(self.free):
+            if e - s >= need:
+                if e - s == need:
+                    self.free.pop(k)
+                else:
+                    self.free[k][0] = s + need
+                return s
+        return None
+
+    def release(self, start: int, n: int) -> None:
+        need = (n + ALIGN - 1) // ALIGN * ALIGN
+        k = bisect.bisect_left(self.free, [start, start + need])
+        self.free.insert(k, [start, start + need])
+        merged: List[List[int]] = []
+        for s, e in self.free:
+            if merged and merged[-1][1] == s:
+                merged[-1][1] = e
+            else:
+                merged.append([s, e])
+        self.free = merged
+
+    def used(self) -> int:
+        return self.capacity - sum(e - s for s, e in self.free)
+
+
+@dataclass
+class RequestResult:
+    rid: int
+    arrival_s: float
+    admit_s: float = 0.0
+    done_s: float = 0.0
+    photons: int = 0
+    photon_steps: int = 0
+    status: Optional[np.ndarray] = None
+    x: Optional[np.ndarray] = None      # (8, n) final state (double; FP32C: hi + lo)
+    steps: Optional[np.ndarray] = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+def bytes_per_photon(precision: str) -> int:
+    """HBM footprint of one resident photon: state (FP64 64 B, FP32C 32 B hi +
+    32 B lo), status/steps/camera (12 B), counters (12 B), classify flag (1 B)."""
+    return 64 + 12 + 12 + 1
+
+
+@dataclass
+class Server:
+    """Resident pool + slot table + iteration loop."""
+    budget_bytes: int
+    params: Params = field(default_factory=lambda: Params(precision="fp32c"))
+    max_slots: int = 64
+    slice_ms: float = 40.0
+    keep_results: bool = False
+    device: str = "cuda"
+
+    def __post_init__(self):
+        import torch
+        self.torch = torch
+        cap = self.budget_bytes // bytes_per_photon(self.params.precision)
+        self.capacity = max(ALIGN, cap // ALIGN * ALIGN)
+        S = self.capacity
+        fp64 = self.params.precision == "fp64"
+        dt = torch.float64 if fp64 else torch.float32
+        dev = self.device
+        self.x = torch.zeros(8 * S, dtype=dt, device=dev)
+        self.lo = None if fp64 else torch.zeros(8 * S, dtype=torch.float32, device=dev)
+        # Photons outside every slot stay in a terminal status (ignored).
+        self.status = torch.full((S,), G.UNFINISHED, dtype=torch.int32, device=dev)
+        self.steps = torch.zeros(S, dtype=torch.int32, device=dev)
+        self.cam = torch.zeros(S, dtype=torch.int32, device=dev)
+        self.counters = torch.zeros(3 * S, dtype=torch.int32, device=dev)
+        self.flag = torch.zeros(S, dtype=torch.int8, device=dev)
+        self.counts = torch.zeros(5 * self.max_slots, dtype=torch.int32, device=dev)
+        self.counts_host = torch.zeros(5 * self.max_slots, dtype=torch.int32, pin_memory=True)
+        # Work lists of live photon ids (double-buffered) and their lengths.
+        self.work = [torch.zeros(S + G.GRAY_WORKLIST_SLACK, dtype=torch.int32, device=dev)
+                     for _ in range(2)]
+        self.work_count = torch.zeros(2, dtype=torch.int32, device=dev)
+        # photons of each slot that have stopped (updated by the integrator)
+        self.cam_done = torch.zeros(self.max_slots, dtype=torch.int32, device=dev)
+        self.done_host = torch.zeros(self.max_slots, dtype=torch.int32, pin_memory=True)
+        self.state = G.gray_state(self.x.data_ptr(), None if fp64 else self.lo.data_ptr(),
+                                  self.status.data_ptr(), self.steps.data_ptr(), self.cam.data_ptr(),
+                                  self.counters.data_ptr(), None, None, S, S)
+        self.state.cam_done = self.cam_done.data_ptr()
+        self._cur = 0
+        self._bind_work()
+        self.p = G.params_struct(self.params)
+        self.p.flags |= G.GRAY_SLOTS | G.GRAY_WORKLIST
+        self.slots = (G.gray_camera * self.max_slots)()
+        for k in range(self.max_slots):
+            self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0)
+        ws = G.gray_workspace_size(S, self.max_slots, self.p)
+        self._ws = torch.zeros(ws + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = self._ws.data_ptr() + (-self._ws.data_ptr()) % 256
+        self.ws_bytes = ws
+        self.result_struct = G.gray_result(self.flag.data_ptr(), None, None, self.counts.data_ptr())
+        self.alloc = RangeAllocator(S)
+        self.stream = torch.cuda.current_stream().cuda_stream
+        self.active: Dict[int, tuple] = {}     # slot -> (Request, first, n, RequestResult)
+        self.call_steps = 64
+        self.iterations = 0
+        self.max_active = 0
+        self.max_used = 0
+        self.admit_order: List[int] = []
+
+    def _bind_work(self) -> None:
+        """work_in = list `_cur` (read by the next integrate, appended to by
+        admissions), work_out = the other list."""
+        a, b = self._cur, 1 - self._cur
+        cp = self.work_count.data_ptr()
+        self.state.work_in = self.work[a].data_ptr()
+        self.state.work_out = self.work[b].data_ptr()
+        self.state.work_in_count = cp + 4 * a
+        self.state.work_out_count = cp + 4 * b
+
+    # ------------------------------------------------------------ pool ops
+    def _admit(self, req: Request, now: float) -> bool:
+        c = req.camera
+        n = c.nx * c.ny
+        if n > self.capacity:
+            raise ValueError(f"request {req.rid} ({n} photons) exceeds the pool")
+        free_slots = [k for k in range(self.max_slots) if k not in self.active]
+        if not free_slots:
+            return False
+        first = self.alloc.alloc(n)
+        if first is None:
+            return False
+        k = free_slots[0]
+        self.slots[k] = G.gray_camera(c.a, c.r_obs, c.incl, c.nx, c.ny, c.alpha_lo, c.alpha_hi,
+                                      c.beta_lo, c.beta_hi, first)
+        G.gray_camera_init_slot(self.slots, self.max_slots, k, self.p, self.state, self.stream)
+        res = RequestResult(req.rid, req.arrival_s, admit_s=now, photons=n)
+        self.active[k] = (req, first, n, res)
+        self.admit_order.append(req.rid)
+        self.max_active = max(self.max_active, len(self.active))
+        self.max_used = max(self.max_used, self.alloc.used())
+        return True
+
+    def _retire(self, k: int, now: float) -> RequestResult:
+        req, first, n, res = self.active.pop(k)
+        torch = self.torch
+        st = self.steps[first:first + n]
+        res.photon_steps = int(st.to(torch.int64).sum().item())
+        if self.keep_results:
+            res.status = self.status[first:first + n].cpu().numpy()
+            res.steps = st.cpu().numpy()
+            rows = self.x.view(8, self.capacity)[:, first:first + n].double()
+            if self.lo is not None:
+                rows = rows + self.lo.view(8, self.capacity)[:, first:first + n].double()
+            res.x = rows.cpu().numpy()
+        # free the range: its photons stay terminal (status is not RUNNING)
+        self.alloc.release(first, n)
+        self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0)
+        res.done_s = now
+        return res
+
+    def _iterate(self) -> float:
+        """One integrate launch over every in-flight request, then per-slot
+        status counts. Returns the wall time of the iteration in ms."""
+        torch = self.torch
+        t0 = time.perf_counter()
+        self.p.call_steps = int(self.call_steps)
+        G.gray_integrate(self.slots, self.max_slots, self.p, self.state, self.ws_ptr, self.ws_bytes,
+                         self.stream)
+        self._cur = 1 - self._cur          # the ids still running are the next input
+        self._bind_work()
+        self.iterations += 1
+        self.done_host.copy_(self.cam_done, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        dt = (time.perf_counter() - t0) * 1e3
+        # aim the next iteration at slice_ms
+        scale = self.slice_ms / max(dt, 1e-3)
+        self.call_steps = int(min(4096, max(32, self.call_steps * min(4.0, max(0.25, scale)))))
+        return dt
+
+    # -------------------------------------------------------------- driver
+    def run(self, requests: Sequence[Request], realtime: bool = True,
+            on_done=None) -> List[RequestResult]:
+        """Serve `requests` (sorted by arrival). With realtime=False every
+        request is available at once (closed loop, for saturation)."""
+        pending = list(requests)
+        waiting: List[Request] = []
+        done: List[RequestResult] = []
+        t_start = time.perf_counter()
+        i = 0
+        while i < len(pending) or waiting or self.active:
+            now = time.perf_counter() - t_start
+            while i < len(pending) and (not realtime or pending[i].arrival_s <= now):
+                waiting.append(pending[i])
+                i += 1
+            while waiting and self._admit(waiting[0], now):
+                waiting.pop(0)
+            if not self.active:
+                if i < len(pending):
+                    time.sleep(max(0.0, pending[i].arrival_s - (time.perf_counter() - t_start)))
+                continue
+            self._iterate()
+            now = time.perf_counter() - t_start
+            done_counts = self.done_host.numpy()
+            for k in list(self.active.keys()):
+                if done_counts[k] == self.active[k][2]:
+                    r = self._retire(k, now)
+                    done.append(r)
+                    if on_done:
+                        on_done(r)
+        return done
+
+
+def latency_stats(results: Sequence[RequestResult], skip: int = 0) -> dict:
+    rs = sorted(results, key=lambda r: r.rid)[skip:]
+    lat = np.array([r.latency_s for r in rs]) * 1e3
+    steps = sum(r.photon_steps for r in rs)
+    span = max(r.done_s for r in rs) - min(r.arrival_s for r in rs)
+    return {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "photon_steps_per_s": steps / span, "span_s": span,
+            "photons": int(sum(r.photons for r in rs))}
