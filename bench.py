@@ -43,11 +43,41 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1,
                     help="oracle traces every k-th row and column of the grid")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
     ap.add_argument("--serve-requests", type=int, default=1100)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-precision", choices=["fp64", "fp32c"], default="fp32c")
     return ap.parse_args()
+
+
+def sweep(G, W, torch, np) -> dict:
+    """The 256-camera sweep (side log-uniform in [64, 1024], spin U[0, 0.998],
+    inclination U[1, 89] deg, seeded per camera) in one persistent launch per
+    precision: integrate time and ns per photon-step."""
+    cams = W.sweep_cameras()
+    out = {"cameras": len(cams), "photons": int(sum(c.n for c in cams))}
+    t = {}
+    for prec in ("fp64", "fp32c"):
+        b = G.Batch(cams, W.Params(precision=prec), counters=True, mark=False)
+        ms = []
+        for rep in range(2):
+            b.camera_init()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.integrate()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        steps = int(b.steps[: b.n].to(torch.int64).sum().item())
+        t[prec] = min(ms)
+        out[prec] = {"integrate_ms": min(ms), "photon_steps": steps,
+                     "ns_per_photon_step": min(ms) * 1e6 / steps,
+                     "tflops": F_STEP[prec] * steps / (min(ms) * 1e-3) / 1e12}
+        del b
+        torch.cuda.empty_cache()
+    out["fp32c_speedup_vs_fp64"] = t["fp64"] / t["fp32c"]
+    return out
 
 
 def serving(args) -> dict:
@@ -229,6 +259,9 @@ def main():
                      "status_counts": other["status"], "drift_ELQ": other["drift"]},
         "fp32c_speedup_vs_fp64": t64 / t32,
     }
+    if not args.no_sweep:
+        print("bench: 256-camera sweep", file=sys.stderr, flush=True)
+        out["sweep"] = sweep(G, W, torch, np)
     if not args.no_serve:
         print("bench: serving", file=sys.stderr, flush=True)
         out["serving"] = serving(args)
