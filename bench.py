@@ -33,6 +33,25 @@ F_STEP = {"fp64": 644, "fp32c": 644}
 PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 
 
+def measured_traffic(prec: str):
+    """HBM bytes per integrate launch on this workload from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources
+    changed since those counters were taken."""
+    from paper_1303_5057_amd.srchash import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", "k_integrate_kerr512_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()[:2]
+        vals[k] = v
+    if vals.get("source_hash") != kernel_source_hash() or prec not in vals:
+        return None
+    return float(vals[prec])
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +63,9 @@ def parse():
                     help="oracle traces every k-th row and column of the grid")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain device copy of 256 MiB (read 256 MiB, write "
+                         "256 MiB), the reference for the HBM traffic counters")
     ap.add_argument("--serve-requests", type=int, default=1100)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
@@ -214,6 +236,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 3
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     cam = W.C2
     print("bench: timing the 512x512 workload", file=sys.stderr, flush=True)
     head = measure(G, W, torch, np, cam, args.precision, args.steps, args.warmup)
@@ -250,7 +279,8 @@ def main():
         "euler_fallback_steps": head["euler_steps"],
         "drift_ELQ": head["drift"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.precision),
+                     "traffic_unit": "bytes per launch", "kernel": kernel,
                      "flops_per_photon_step": F_STEP[args.precision]},
         other_prec: {"ns_per_photon_step": other["ms_per_step"] * 1e6 / other["total_steps"],
                      "integrate_ms": other["integrate_ms"],
