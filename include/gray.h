@@ -183,8 +183,9 @@ typedef struct {
 } gray_result;
 
 /* Bytes of device workspace that gray_integrate needs for n photons over ncam
- * cameras (per-camera constants and the photon work queue). Returns 0 on
- * invalid arguments. */
+ * cameras: per-camera constants and the queue counter, plus, without
+ * GRAY_WORKLIST, the launch order (5 bytes per photon and a fixed 256 KiB of
+ * histograms). Returns 0 on invalid arguments. */
 size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params *p);
 
 /* Image plane -> initial state (Sec. 2 defers the set-up; see the camera
@@ -205,8 +206,11 @@ int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int32_t slot,
  * captured, escapes, turns non-finite or reaches max_steps (or until it has
  * taken call_steps steps in this call). Photons of all cameras share one
  * persistent launch; a wave refills lanes whose photon finished from a global
- * queue. Resumable: the state is the checkpoint, and repeated calls with
- * call_steps > 0 reproduce a single call exactly (bit for bit in FP64).
+ * queue. Without GRAY_WORKLIST the queue holds the running photons ordered
+ * so that those whose constants of motion lie nearest a spherical photon
+ * orbit (the longest trajectories) start first; the order never changes a
+ * photon's result. Resumable: the state is the checkpoint, and repeated calls
+ * with call_steps > 0 reproduce a single call exactly (bit for bit in FP64).
  * workspace: device memory of gray_workspace_size() bytes, 256-byte aligned. */
 int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p,
                    gray_state *s, void *workspace, size_t workspace_bytes, void *hip_stream);

@@ -9,9 +9,11 @@
 // GPU design: one photon per lane of a 64-wide wavefront, state in VGPRs for
 // the whole trajectory, structure-of-arrays state in HBM read once and written
 // once per photon. The integrate kernel is persistent: a wave holds 64 photons,
-// and whenever enough lanes have finished it hands them the next photons of a
-// 64-photon chunk taken from one global counter (one atomic per 64 photons),
-// so lanes stay busy while step counts differ per photon.
+// and whenever lanes have finished it hands them the next photon ids of a
+// chunk taken from one global counter, so lanes stay busy while step counts
+// differ per photon. The ids come from the caller's work list or, in dense
+// mode, from a launch order that starts the photons expected to take the most
+// steps first (k_order_key).
 #include "../../include/gray.h"
 #include "kerr.hpp"
 
@@ -53,8 +55,20 @@ constexpr unsigned kMaxGrab = 8;       // refill rounds per queue grab, at most
 constexpr unsigned kSpan = 512;        // work-list ids reserved per append grab
 constexpr int64_t kMaxListWaves = 2048; // waves of a work-list launch, at most
 static_assert(kMaxListWaves * kSpan <= GRAY_WORKLIST_SLACK, "list slack covers every wave's last span");
-constexpr size_t kWsHeader = 256;      // queue counter, padded
+constexpr size_t kWsHeader = 512;      // WsHeader, padded
+constexpr int kOrderBins = 32;         // scheduling-key buckets
+constexpr unsigned kOrderBlocks = 2048; // blocks of the ordering passes, at most
 constexpr int64_t kMaxPhotons = (int64_t)1 << 31;
+
+// Start of the workspace: queue counter and the ordering pass's counts.
+struct WsHeader {
+    unsigned queue;                 // next queue position
+    unsigned count;                 // photons in the launch order
+    unsigned pad[30];
+    unsigned hist[kOrderBins];      // running photons per key bucket
+    unsigned cursor[kOrderBins];    // positions handed out per bucket
+};
+static_assert(sizeof(WsHeader) <= kWsHeader, "header fits its reserved space");
 
 // Per-camera constants the integrator needs, kept in the workspace.
 struct DevCam {
@@ -167,13 +181,140 @@ __global__ __launch_bounds__(kBlock) void k_camera_init(InitArgs A)
 }
 
 // ------------------------------------------------------------ workspace setup
-__global__ void k_setup(DevCam *table, unsigned *queue, unsigned *work_out_count, SetupChunk ch)
+__global__ void k_setup(DevCam *table, WsHeader *hdr, unsigned *work_out_count, SetupChunk ch)
 {
     const int j = threadIdx.x;
     if (j < ch.count) table[ch.base + j] = ch.c[j];
-    if (ch.base == 0 && j == 0) {
-        *queue = 0u;
-        if (work_out_count) *work_out_count = 0u;
+    if (ch.base == 0) {
+        if (j < kOrderBins) {
+            hdr->hist[j] = 0u;
+            hdr->cursor[j] = 0u;
+        }
+        if (j == 0) {
+            hdr->queue = 0u;
+            hdr->count = 0u;
+            if (work_out_count) *work_out_count = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------ launch order
+// Step counts differ by two orders of magnitude between photons, and a launch
+// lasts at least as long as its longest photon takes after it starts. The
+// longest ones are those that circle the hole near a spherical photon orbit,
+// so the dense-mode launch hands out photons in increasing order of how close
+// their constants of motion are to such an orbit. The order changes which
+// lane advances a photon and when, never the photon's result.
+//
+// Key: with lam = L / E and eta = Q / E^2 the radial potential is
+//   R(r) = r^4 + (a^2 - eta - lam^2) r^2 + 2 (eta + (lam - a)^2) r - a^2 eta,
+// and a double root of R outside the horizon is a spherical photon orbit.
+// The key is |R| / r^4 at R's outer local minimum (not inside the horizon),
+// or 1 when R has no local minimum at r > 0.
+__device__ double orbit_key(double a, double rbh, const State<double> &x)
+{
+    double E, L, Q;
+    conserved(a, x, E, L, Q);
+    const double lam = L / E, eta = Q / (E * E);
+    const double A2 = a * a - eta - lam * lam;
+    const double B1 = 2.0 * (eta + (lam - a) * (lam - a));
+    const double C0 = -a * a * eta;
+    if (!(A2 < 0.0)) return 1.0;
+    // R'(r) = 4 r^3 + 2 A2 r + B1 is convex right of R's inflection point
+    // ri; a local minimum of R exists there iff R'(ri) < 0, and Newton's
+    // method from r0 = sqrt(-A2 / 2) > ri converges to it without leaving
+    // the convex part.
+    const double ri = sqrt(-A2 / 6.0);
+    if (!((4.0 * ri * ri + 2.0 * A2) * ri + B1 < 0.0)) return 1.0;
+    double r = sqrt(-A2 / 2.0);
+    for (int k = 0; k < 8; ++k) r -= ((4.0 * r * r + 2.0 * A2) * r + B1) / (12.0 * r * r + 2.0 * A2);
+    r = fmax(r, rbh);
+    const double r2 = r * r;
+    return fabs(((r2 + A2) * r2 + B1 * r + C0) / (r2 * r2));
+}
+
+// Bucket of a key: its binary exponent, so keys 2^-24 .. 2^7 spread over
+// kOrderBins buckets; non-finite keys go last.
+__device__ __forceinline__ unsigned order_bucket(double key)
+{
+    if (!(key < 128.0)) return kOrderBins - 1;
+    if (key < 0x1p-24) return 0;
+    int e;
+    frexp(key, &e);
+    return (unsigned)min(max(e + 24, 0), kOrderBins - 1);
+}
+
+struct OrderArgs {
+    const void *x, *lo;
+    const int32_t *status, *cam;
+    const DevCam *cams;
+    uint8_t *bucket;        // per photon: key bucket, or 0xff when not running
+    unsigned *block_hist;   // per ordering block and bucket
+    int32_t *perm;          // launch order of the running photons
+    WsHeader *hdr;
+    int64_t n, stride, per_block;
+    int32_t precision, pad;
+};
+
+// Pass 1: bucket of every running photon, per-block and global histograms.
+__global__ __launch_bounds__(kBlock) void k_order_key(OrderArgs A)
+{
+    __shared__ unsigned h[kOrderBins];
+    if (threadIdx.x < kOrderBins) h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * A.per_block;
+    const int64_t i1 = i0 + A.per_block < A.n ? i0 + A.per_block : A.n;
+    const int64_t S = A.stride;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        unsigned b = 0xffu;
+        if (A.status[i] == GRAY_RUNNING) {
+            State<double> x;
+            double v[8];
+            if (A.precision == GRAY_FP64) {
+                const double *X = (const double *)A.x;
+                for (int k = 0; k < 8; ++k) v[k] = X[k * S + i];
+            } else {
+                const float *H = (const float *)A.x, *L = (const float *)A.lo;
+                for (int k = 0; k < 8; ++k) v[k] = (double)H[k * S + i] + (double)L[k * S + i];
+            }
+            x.t = v[0]; x.r = v[1]; x.th = v[2]; x.ph = v[3];
+            x.kt = v[4]; x.kr = v[5]; x.kth = v[6]; x.kph = v[7];
+            const DevCam cm = A.cams[A.cam[i]];
+            b = order_bucket(orbit_key(cm.a, cm.rbh, x));
+            atomicAdd(&h[b], 1u);
+        }
+        A.bucket[i] = (uint8_t)b;
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderBins) {
+        const unsigned c = h[threadIdx.x];
+        A.block_hist[(int64_t)blockIdx.x * kOrderBins + threadIdx.x] = c;
+        if (c) {
+            atomicAdd(&A.hdr->hist[threadIdx.x], c);
+            atomicAdd(&A.hdr->count, c);
+        }
+    }
+}
+
+// Pass 2: each block reserves, per bucket, room for its photons after the
+// buckets before it, then writes their ids (any order inside a bucket).
+__global__ __launch_bounds__(kBlock) void k_order_scatter(OrderArgs A)
+{
+    __shared__ unsigned base[kOrderBins], run[kOrderBins];
+    const unsigned j = threadIdx.x;
+    if (j < kOrderBins) {
+        unsigned start = 0;
+        for (unsigned k = 0; k < j; ++k) start += A.hdr->hist[k];
+        const unsigned c = A.block_hist[(int64_t)blockIdx.x * kOrderBins + j];
+        base[j] = c ? start + atomicAdd(&A.hdr->cursor[j], c) : 0u;
+        run[j] = 0u;
+    }
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * A.per_block;
+    const int64_t i1 = i0 + A.per_block < A.n ? i0 + A.per_block : A.n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const unsigned b = A.bucket[i];
+        if (b < (unsigned)kOrderBins) A.perm[base[b] + atomicAdd(&run[b], 1u)] = (int32_t)i;
     }
 }
 
@@ -187,7 +328,7 @@ struct IntArgs {
     double *mark, *disk;
     const DevCam *cams;
     unsigned *queue;
-    const int32_t *work_in;     // work-list mode: ids to advance, count at *work_in_count
+    const int32_t *work_in;     // ids to advance (the caller's work list or the launch order), count at *work_in_count
     int32_t *work_out;          // ids still running at the end, count at *work_out_count
     const unsigned *work_in_count;
     unsigned *work_out_count;
@@ -300,8 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 
     unsigned chunk_next = 0, chunk_end = 0;
     bool exhausted = false;
-    // Queue length: all photon ids, or the length of the work list.
-    const int64_t nq = A.work_in ? (int64_t)__builtin_amdgcn_readfirstlane(*A.work_in_count) : A.n;
+    // Queue length: the length of the work list or of the launch order.
+    const int64_t nq = (int64_t)__builtin_amdgcn_readfirstlane(*A.work_in_count);
     // A grab takes `grab` ids (a multiple of 64): large enough to keep the
     // single queue counter off the critical path, small enough that every wave
     // gets about four grabs.
@@ -328,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 const unsigned rank = lane_rank(idle);
                 if (!active && rank < avail) {
                     const unsigned q = chunk_next + rank;
-                    id = A.work_in ? (int64_t)A.work_in[q] : (int64_t)q;
+                    id = (int64_t)A.work_in[q];
                     if (id >= 0 && A.status[id] == GRAY_RUNNING) {
                         L.load(A, id);
                         const DevCam cm = A.cams[A.cam[id]];
@@ -755,14 +896,40 @@ static int device_info(DeviceInfo &out)
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Workspace: header, camera table, then (dense mode only) the ordering
+// pass's per-block histograms, launch order and buckets. Offsets are
+// multiples of 256 bytes.
+struct WsLayout {
+    size_t table, block_hist, perm, bucket, total;
+};
+
+static WsLayout ws_layout(int64_t n, int32_t ncam, uint32_t flags)
+{
+    WsLayout L{};
+    L.table = kWsHeader;
+    size_t off = L.table + round_up((size_t)ncam * sizeof(DevCam), 256);
+    if (!(flags & GRAY_WORKLIST)) {
+        L.block_hist = off;
+        off += round_up((size_t)kOrderBlocks * kOrderBins * sizeof(unsigned), 256);
+        L.perm = off;
+        off += round_up((size_t)n * sizeof(int32_t), 256);
+        L.bucket = off;
+        off += round_up((size_t)n, 256);
+    }
+    L.total = off;
+    return L;
+}
+
 } // namespace gray
 
 using namespace gray;
 
 extern "C" size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params *p)
 {
-    if (n < 0 || ncam < 1 || validate_params(p) != GRAY_OK) return 0;
-    return kWsHeader + (size_t)ncam * sizeof(DevCam);
+    if (n < 0 || n >= kMaxPhotons || ncam < 1 || validate_params(p) != GRAY_OK) return 0;
+    return ws_layout(n, ncam, p->flags).total;
 }
 
 static int launch_init(const gray_camera *cams, int32_t k0, int32_t cnt, const gray_params *p,
@@ -833,8 +1000,11 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     DeviceInfo dev;
     if ((e = device_info(dev))) return e;
     hipStream_t st = (hipStream_t)hip_stream;
-    unsigned *queue = (unsigned *)workspace;
-    DevCam *table = (DevCam *)((char *)workspace + kWsHeader);
+    const bool wl = (p->flags & GRAY_WORKLIST) != 0;
+    const WsLayout W = ws_layout(s->n, ncam, p->flags);
+    char *ws = (char *)workspace;
+    WsHeader *hdr = (WsHeader *)ws;
+    DevCam *table = (DevCam *)(ws + W.table);
 
     for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk) {
         SetupChunk ch;
@@ -852,9 +1022,34 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
             d.disk_rmin = p->disk_rmin < 0.0 ? isco_radius(c.a) : p->disk_rmin;
             d.disk_rmax = p->disk_rmax;
         }
-        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, queue,
-                           (p->flags & GRAY_WORKLIST) ? s->work_out_count : (unsigned *)nullptr, ch);
+        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, hdr,
+                           wl ? s->work_out_count : (unsigned *)nullptr, ch);
         if ((e = check_launch("setup launch"))) return e;
+    }
+
+    if (!wl) {
+        // Launch order of the running photons (see k_order_key).
+        OrderArgs O;
+        memset(&O, 0, sizeof O);
+        O.x = s->x;
+        O.lo = s->lo;
+        O.status = s->status;
+        O.cam = s->cam;
+        O.cams = table;
+        O.bucket = (uint8_t *)(ws + W.bucket);
+        O.block_hist = (unsigned *)(ws + W.block_hist);
+        O.perm = (int32_t *)(ws + W.perm);
+        O.hdr = hdr;
+        O.n = s->n;
+        O.stride = s->stride;
+        O.precision = p->precision;
+        const int64_t blocks = std::min<int64_t>(kOrderBlocks, blocks_for(s->n));
+        O.per_block = (int64_t)round_up((size_t)((s->n + blocks - 1) / blocks), kBlock);
+        const unsigned og = (unsigned)((s->n + O.per_block - 1) / O.per_block);
+        hipLaunchKernelGGL(k_order_key, dim3(og), dim3(kBlock), 0, st, O);
+        if ((e = check_launch("order key launch"))) return e;
+        hipLaunchKernelGGL(k_order_scatter, dim3(og), dim3(kBlock), 0, st, O);
+        if ((e = check_launch("order scatter launch"))) return e;
     }
 
     IntArgs A;
@@ -868,12 +1063,15 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.mark = s->mark;
     A.disk = s->disk;
     A.cams = table;
-    A.queue = queue;
-    if (p->flags & GRAY_WORKLIST) {
+    A.queue = &hdr->queue;
+    if (wl) {
         A.work_in = s->work_in;
         A.work_out = s->work_out;
         A.work_in_count = s->work_in_count;
         A.work_out_count = s->work_out_count;
+    } else {
+        A.work_in = (const int32_t *)(ws + W.perm);
+        A.work_in_count = &hdr->count;
     }
     A.cam_done = s->cam_done;
     A.n = s->n;
@@ -892,8 +1090,7 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[p->precision];
     // In work-list mode the list length is only known on the device; the grid
     // is capped at kMaxListWaves waves, which bounds the unused list tail.
-    const int64_t need = (p->flags & GRAY_WORKLIST) ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave))
-                                                    : blocks_for(s->n);
+    const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave)) : blocks_for(s->n);
     const unsigned grid = (unsigned)(need < resident ? need : resident);
     if (p->precision == GRAY_FP64)
         hipLaunchKernelGGL(k_integrate<GRAY_FP64>, dim3(grid), dim3(kBlock), 0, st, A);

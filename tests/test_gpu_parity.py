@@ -98,6 +98,34 @@ def test_resume_is_bitwise(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_launch_order_covers_running_photons_once(prec):
+    """The dense-mode queue (running photons ordered by their distance to a
+    spherical photon orbit) holds every running photon exactly once: with
+    call_steps = 1 each running photon advances one step, a stopped one none
+    (a photon handed out twice would restart its count and step twice)."""
+    import torch
+    cams = [W.scaled(W.C2, 33, 29), W.scaled(W.C1, 17, 21),
+            W.Camera(0.5, 1000.0, 1.2, 40, 9, -7.0, 7.0, -3.0, 3.0)]
+    b = G.Batch(cams, W.Params(precision=prec))
+    b.camera_init()
+    n = b.n
+    gen = torch.Generator().manual_seed(20261202)
+    stopped = torch.randperm(n, generator=gen)[: n // 3].to(b.status.device)
+    b.status[stopped] = G.CAPTURED
+    b.set_call_steps(1)
+    for k in range(3):
+        b.integrate()
+        torch.cuda.synchronize()
+        steps = b.steps[:n].cpu().numpy()
+        st = b.status[:n].cpu().numpy()
+        mask = np.zeros(n, bool)
+        mask[stopped.cpu().numpy()] = True
+        assert np.all(steps[mask] == 0)
+        assert np.all(steps[~mask] == k + 1)
+        assert np.all(st[~mask] == G.RUNNING)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_unfinished_and_nonfinite(prec):
     import torch
     cam = W.scaled(W.C2, 16)
