@@ -207,9 +207,9 @@ int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int32_t slot,
  * taken call_steps steps in this call). Photons of all cameras share one
  * persistent launch; a wave refills lanes whose photon finished from a global
  * queue. Without GRAY_WORKLIST the queue holds the running photons ordered
- * so that those whose constants of motion lie nearest a spherical photon
- * orbit (the longest trajectories) start first; the order never changes a
- * photon's result. Resumable: the state is the checkpoint, and repeated calls
+ * so that those expected to take the most steps (constants of motion near a
+ * spherical photon orbit, or small |L_z|: paths near the polar axis) start
+ * first; the order never changes a photon's result. Resumable: the state is the checkpoint, and repeated calls
  * with call_steps > 0 reproduce a single call exactly (bit for bit in FP64).
  * workspace: device memory of gray_workspace_size() bytes, 256-byte aligned. */
 int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p,
