@@ -303,7 +303,10 @@ __global__ __launch_bounds__(kBlock) void k_order_key(OrderArgs A)
 }
 
 // Pass 2: each block reserves, per bucket, room for its photons after the
-// buckets before it, then writes their ids (any order inside a bucket).
+// buckets before it, then writes their ids. The lanes of a wave that share
+// a bucket take consecutive positions in lane (= id) order, so the order
+// holds runs of nearby ids and the integrator's state loads stay mostly
+// coalesced; the order of the runs inside a bucket is arbitrary.
 __global__ __launch_bounds__(kBlock) void k_order_scatter(OrderArgs A)
 {
     __shared__ unsigned base[kOrderBins], run[kOrderBins];
@@ -318,9 +321,25 @@ __global__ __launch_bounds__(kBlock) void k_order_scatter(OrderArgs A)
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * A.per_block;
     const int64_t i1 = i0 + A.per_block < A.n ? i0 + A.per_block : A.n;
+    const unsigned lane = threadIdx.x & (kWave - 1);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const unsigned b = A.bucket[i];
-        if (b < (unsigned)kOrderBins) A.perm[base[b] + atomicAdd(&run[b], 1u)] = (int32_t)i;
+        bool todo = b < (unsigned)kOrderBins;
+        for (;;) {
+            const uint64_t m = ballot(todo);
+            if (m == 0ull) break;
+            const int lead = __ffsll((long long)m) - 1;
+            const unsigned bl = (unsigned)__shfl((int)b, lead, kWave);
+            const bool mine = todo && b == bl;
+            const uint64_t same = ballot(mine);
+            unsigned at = 0;
+            if ((int)lane == lead) at = atomicAdd(&run[bl], (unsigned)__popcll(same));
+            at = (unsigned)__shfl((int)at, lead, kWave);
+            if (mine) {
+                A.perm[base[bl] + at + lane_rank(same)] = (int32_t)i;
+                todo = false;
+            }
+        }
     }
 }
 
