@@ -171,10 +171,28 @@ def cpu_baseline(cam, params, every: int):
     res = oracle.run(p, cam.a, X0, nthreads=threads)
     dt = time.perf_counter() - t0
     nsteps = int(res.steps.sum())
+    # one thread on the 64 x 64 Schwarzschild grid (full grid)
+    c1 = W.C1
+    X1 = oracle.camera_grid(c1.a, c1.r_obs, c1.incl, c1.nx, c1.ny, c1.alpha_lo, c1.alpha_hi,
+                            c1.beta_lo, c1.beta_hi)
+    t1 = time.perf_counter()
+    r1 = oracle.run(p, c1.a, X1, nthreads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": dt * 1e9 / nsteps, "unit": "ns/photon/step", "cores": threads,
             "kind": "oracle",
             "sample": f"every {every} row(s) and column(s) of the 512x512 grid "
-                      f"({len(ids)} rays, {nsteps} photon-steps, {dt:.2f} s wall)"}
+                      f"({len(ids)} rays, {nsteps} photon-steps, {dt:.2f} s wall)",
+            "per_core_ns_per_photon_step": dt * 1e9 / nsteps * threads,
+            "single_thread_64x64_schwarzschild_ns_per_photon_step": dt1 * 1e9 / int(r1.steps.sum()),
+            "nproc": os.cpu_count(), "cpu_model": model}
 
 
 def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
@@ -184,6 +202,7 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
 
     def one_pass(ev0=None, ev1=None):
         b.camera_init()
+        b.wave_iters.zero_()
         if ev0 is not None:
             ev0.record()
         b.integrate()
@@ -206,6 +225,7 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
     ms_per_step = (t1 - t0) * 1e3 / steps
     int_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
     total_steps = int(b.steps[: b.n].to(torch.int64).sum().item())
+    lane_eff = total_steps / (64.0 * max(1, int(b.wave_iters.item())))
     counters = b.counters.view(3, b.stride)[:, : b.n].to(torch.int64).sum(dim=1).tolist()
     status = b.status[: b.n].cpu().numpy()
     cons = res.cons.view(9, b.stride)[:, : b.n].cpu().numpy()
@@ -218,13 +238,14 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
                        for q, pq in (("p50", 50), ("p99", 99), ("max", 100))} if d.size else {}
     return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
             "total_steps": total_steps, "status": np.bincount(status, minlength=5).tolist(),
-            "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n}
+            "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n,
+            "lane_efficiency": lane_eff}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(photons are independent; a multi-GPU run would shard the ray ids).", file=sys.stderr)
         return 2
     import numpy as np
@@ -277,6 +298,7 @@ def main():
         "integrate_ns_per_photon_step": head["integrate_ms"] * 1e6 / total_steps,
         "status_counts": head["status"],
         "euler_fallback_steps": head["euler_steps"],
+        "lane_efficiency": head["lane_efficiency"],
         "drift_ELQ": head["drift"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(args.precision),
@@ -286,6 +308,7 @@ def main():
                      "integrate_ms": other["integrate_ms"],
                      "photon_steps_per_pass": other["total_steps"],
                      "fp64_step_fraction": other["fp64_steps"] / other["total_steps"],
+                     "lane_efficiency": other["lane_efficiency"],
                      "status_counts": other["status"], "drift_ELQ": other["drift"]},
         "fp32c_speedup_vs_fp64": t64 / t32,
     }

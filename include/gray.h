@@ -166,6 +166,11 @@ typedef struct {
                              stopped in a terminal status; camera_init (and
                              camera_init_slot for its slot) zeroes the entry,
                              gray_integrate adds to it as photons stop       */
+    uint64_t *wave_iters; /* optional [1]: gray_integrate adds the number of
+                             loop iterations its waves ran with at least one
+                             photon (each advances every busy lane by one
+                             step); the caller zeroes it. Lane efficiency of
+                             a call = photon-steps / (64 * wave_iters)       */
 } gray_state;
 
 /* Outputs of gray_classify, all device memory, all rows `stride` apart

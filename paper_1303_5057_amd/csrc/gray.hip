@@ -358,6 +358,7 @@ struct IntArgs {
     const unsigned *work_in_count;
     unsigned *work_out_count;
     unsigned *cam_done;         // per-camera count of photons that stopped
+    unsigned long long *wave_iters; // += loop iterations with a busy lane
     int64_t n, stride;
     double step_frac, xi_eps, euler_div, r_escape;
     double fp64_horizon, fp64_pole, fp64_turn;
@@ -487,6 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     const unsigned grab = (unsigned)rounds * kQueueChunk;
     // Work-list output: a private span of kSpan reserved slots per wave.
     unsigned span_next = 0, span_end = 0;
+    unsigned long long iters = 0;
 
     for (;;) {
         const uint64_t idle = ballot(!active);
@@ -559,11 +561,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 // mark the unused rest of this wave's output span
                 if (A.work_out)
                     for (unsigned j = span_next + lane; j < span_end; j += kWave) A.work_out[j] = -1;
+                if (A.wave_iters && lane == 0 && iters) atomicAdd(A.wave_iters, iters);
                 break;
             }
         }
 
         bool stop_now = false, keep = false;
+        iters += ballot(active) != 0ull;
         if (active) {
             const State<double> xp = L.value();
             State<double> x;
@@ -1128,6 +1132,7 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
         A.two_ended = 1;
     }
     A.cam_done = s->cam_done;
+    A.wave_iters = (unsigned long long *)s->wave_iters;
     A.n = s->n;
     A.stride = s->stride;
     A.step_frac = p->step_frac;
@@ -1214,7 +1219,7 @@ extern "C" const char *gray_strerror(int code)
     }
 }
 
-extern "C" int gray_version(void) { return 100; }
+extern "C" int gray_version(void) { return 101; }
 
 extern "C" size_t gray_struct_size(int which)
 {

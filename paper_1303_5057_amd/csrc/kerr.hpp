@@ -74,19 +74,44 @@ GRAY_HD double rcp(double x)
 
 GRAY_HD double quot(double a, double b) { return a * rcp(b); }
 
+// Two Horner chains in z evaluated side by side:
+//   ps = (..((s[0] z + s[1]) z + s[2]) z ..) + s[NS-1]
+//   pc = (..((c[0] z + c[1]) z + c[2]) z ..) + c[NC-1]
+// On the device each step is one VOP3 v_fma_f64 whose addend is a register
+// it does not overwrite. (Written as fma(), the compiler selects the
+// two-address v_fmac_f64, whose accumulator is the addend, and so copies
+// every loop-invariant coefficient into it first: one extra move per step.)
+// One asm statement holds both chains, interleaved, so no wait states are
+// inserted between them; the steps are dependent plain FP64 FMAs.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GRAY_HORNER_STEP(acc, k) "v_fma_f64 %" #acc ", %2, %" #acc ", %" #k "\n\t"
+#endif
+
 // sin and cos of a small angle, |d| <= 1/16, from their Taylor series (sin
 // to d^9, cos to d^8: truncation below 3e-19). The stage offsets of a step
 // obey |d| <= Delta of eq. (2) to first order, so this covers them.
 GRAY_HD void sincos_small(double d, double &sd, double &cd)
 {
     const double z = d * d;
-    double ps = fma(z, 2.755731922398589e-06, -1.984126984126984e-04);
-    ps = fma(z, ps, 8.333333333333333e-03);
-    ps = fma(z, ps, -1.6666666666666666e-01);
+    constexpr double S0 = 2.755731922398589e-06, S1 = -1.984126984126984e-04,
+                     S2 = 8.333333333333333e-03, S3 = -1.6666666666666666e-01;
+    constexpr double C0 = 2.48015873015873e-05, C1 = -1.388888888888889e-03,
+                     C2 = 4.1666666666666664e-02, C3 = -0.5;
+    double ps, pc;
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fma_f64 %0, %2, %3, %4\n\t"
+        "v_fma_f64 %1, %2, %7, %8\n\t"
+        GRAY_HORNER_STEP(0, 5)
+        GRAY_HORNER_STEP(1, 9)
+        GRAY_HORNER_STEP(0, 6)
+        GRAY_HORNER_STEP(1, 10)
+        : "=&v"(ps), "=&v"(pc)
+        : "v"(z), "v"(S0), "v"(S1), "v"(S2), "v"(S3), "v"(C0), "v"(C1), "v"(C2), "v"(C3));
+#else
+    ps = fma(z, fma(z, fma(z, S0, S1), S2), S3);
+    pc = fma(z, fma(z, fma(z, C0, C1), C2), C3);
+#endif
     sd = fma(d * z, ps, d);
-    double pc = fma(z, 2.48015873015873e-05, -1.388888888888889e-03);
-    pc = fma(z, pc, 4.1666666666666664e-02);
-    pc = fma(z, pc, -0.5);
     cd = fma(z, pc, 1.0);
 }
 
@@ -100,22 +125,41 @@ GRAY_HD void sincos_full(double x, double &s, double &c)
     double r = fma(-k, 1.5707963267948966, x);
     r = fma(-k, 6.123233995736766e-17, r);
     const double z = r * r;
-    double ps = fma(z, 2.8114572543455206e-15, -7.647163731819816e-13);
-    ps = fma(z, ps, 1.6059043836821613e-10);
-    ps = fma(z, ps, -2.505210838544172e-08);
-    ps = fma(z, ps, 2.755731922398589e-06);
-    ps = fma(z, ps, -1.984126984126984e-04);
-    ps = fma(z, ps, 8.333333333333333e-03);
-    ps = fma(z, ps, -1.6666666666666666e-01);
+    constexpr double S0 = 2.8114572543455206e-15, S1 = -7.647163731819816e-13,
+                     S2 = 1.6059043836821613e-10, S3 = -2.505210838544172e-08,
+                     S4 = 2.755731922398589e-06, S5 = -1.984126984126984e-04,
+                     S6 = 8.333333333333333e-03, S7 = -1.6666666666666666e-01;
+    constexpr double C0 = -1.5619206968586225e-16, C1 = 4.779477332387385e-14,
+                     C2 = -1.1470745597729725e-11, C3 = 2.08767569878681e-09,
+                     C4 = -2.755731922398589e-07, C5 = 2.48015873015873e-05,
+                     C6 = -1.388888888888889e-03, C7 = 4.1666666666666664e-02, C8 = -0.5;
+    double ps, pc;
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("v_fma_f64 %0, %2, %3, %4\n\t"
+        "v_fma_f64 %1, %2, %11, %12\n\t"
+        GRAY_HORNER_STEP(0, 5)
+        GRAY_HORNER_STEP(1, 13)
+        GRAY_HORNER_STEP(0, 6)
+        GRAY_HORNER_STEP(1, 14)
+        GRAY_HORNER_STEP(0, 7)
+        GRAY_HORNER_STEP(1, 15)
+        GRAY_HORNER_STEP(0, 8)
+        GRAY_HORNER_STEP(1, 16)
+        GRAY_HORNER_STEP(0, 9)
+        GRAY_HORNER_STEP(1, 17)
+        GRAY_HORNER_STEP(0, 10)
+        GRAY_HORNER_STEP(1, 18)
+        GRAY_HORNER_STEP(1, 19)
+        : "=&v"(ps), "=&v"(pc)
+        : "v"(z), "v"(S0), "v"(S1), "v"(S2), "v"(S3), "v"(S4), "v"(S5), "v"(S6), "v"(S7),
+          "v"(C0), "v"(C1), "v"(C2), "v"(C3), "v"(C4), "v"(C5), "v"(C6), "v"(C7), "v"(C8));
+#else
+    ps = S0;
+    for (double sk : {S1, S2, S3, S4, S5, S6, S7}) ps = fma(z, ps, sk);
+    pc = C0;
+    for (double ck : {C1, C2, C3, C4, C5, C6, C7, C8}) pc = fma(z, pc, ck);
+#endif
     const double sr = fma(r * z, ps, r);
-    double pc = fma(z, -1.5619206968586225e-16, 4.779477332387385e-14);
-    pc = fma(z, pc, -1.1470745597729725e-11);
-    pc = fma(z, pc, 2.08767569878681e-09);
-    pc = fma(z, pc, -2.755731922398589e-07);
-    pc = fma(z, pc, 2.48015873015873e-05);
-    pc = fma(z, pc, -1.388888888888889e-03);
-    pc = fma(z, pc, 4.1666666666666664e-02);
-    pc = fma(z, pc, -0.5);
     const double cr = fma(z, pc, 1.0);
     const int q = (int)k & 3;
     const double a = (q & 1) ? cr : sr;

@@ -57,7 +57,8 @@ class gray_state(ctypes.Structure):
                 ("mark", ctypes.c_void_p), ("disk", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("stride", ctypes.c_int64), ("work_in", ctypes.c_void_p),
                 ("work_out", ctypes.c_void_p), ("work_in_count", ctypes.c_void_p),
-                ("work_out_count", ctypes.c_void_p), ("cam_done", ctypes.c_void_p)]
+                ("work_out_count", ctypes.c_void_p), ("cam_done", ctypes.c_void_p),
+                ("wave_iters", ctypes.c_void_p)]
 
 
 class gray_result(ctypes.Structure):
@@ -223,9 +224,13 @@ class Batch:
         off = (-self._ws.data_ptr()) % 256
         self.ws_ptr = self._ws.data_ptr() + off
         self.ws_bytes = ws
+        # loop iterations of the integrator's waves (lane efficiency); the
+        # integrator adds to it, callers zero it
+        self.wave_iters = torch.zeros(1, dtype=torch.int64, device=device)
         self.state = gray_state(_ptr(self.x), _ptr(self.lo), _ptr(self.status), _ptr(self.steps),
                                 _ptr(self.cam), _ptr(self.counters), _ptr(self.mark),
                                 _ptr(self.disk), self.n, S)
+        self.state.wave_iters = _ptr(self.wave_iters)
 
     def set_call_steps(self, k: int) -> None:
         self.p.call_steps = int(k)

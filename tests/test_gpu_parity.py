@@ -126,6 +126,28 @@ def test_launch_order_covers_running_photons_once(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_wave_iteration_counter(prec):
+    """wave_iters counts loop iterations with a busy lane: every iteration
+    advances at most 64 photons by one step, and some wave ran as many
+    iterations as the longest photon took steps."""
+    import torch
+    cam = W.scaled(W.C2, 48, 40)
+    b = G.Batch([cam], W.Params(precision=prec))
+    b.camera_init()
+    b.wave_iters.zero_()
+    b.integrate()
+    torch.cuda.synchronize()
+    it = int(b.wave_iters.item())
+    steps = b.steps[: b.n].to(torch.int64)
+    total, longest = int(steps.sum().item()), int(steps.max().item())
+    assert longest <= it and total <= 64 * it
+    assert 0.05 < total / (64 * it) <= 1.0
+    b.integrate()             # nothing left running: adds nothing
+    torch.cuda.synchronize()
+    assert int(b.wave_iters.item()) == it
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_unfinished_and_nonfinite(prec):
     import torch
     cam = W.scaled(W.C2, 16)
