@@ -63,6 +63,7 @@ def parse():
                     help="oracle traces every k-th row and column of the grid")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
+    ap.add_argument("--no-ring", action="store_true", help="skip the photon-ring study")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 256 MiB (read 256 MiB, write "
                          "256 MiB), the reference for the HBM traffic counters")
@@ -195,6 +196,27 @@ def cpu_baseline(cam, params, every: int):
             "nproc": os.cpu_count(), "cpu_model": model}
 
 
+def ring_study(np) -> dict:
+    """The photon-ring parameter study (16 spins x 19 inclinations, 6000 x 181
+    polar rays each, 3.3e8 rays) in one persistent launch: integrate time,
+    ns per photon-step, and the ring measures against the paper's fits."""
+    from paper_1303_5057_amd import ring as GR
+    rings, timing = GR.study()
+    dR = np.array([r.measures["R_mean"] - GR.paper_fit_mean_radius(r.a, r.incl_deg) for r in rings])
+    dA = np.array([r.measures["A"] - GR.paper_fit_asymmetry(r.a, r.incl_deg) for r in rings])
+    edge_on = [r for r in rings if r.incl_deg == 90]
+    timing.update({
+        "configs": len(rings),
+        "tflops": 644 * timing["photon_steps"] / (timing["integrate_ms"] * 1e-3) / 1e12,
+        "unfinished_rays": int(sum(r.unfinished for r in rings)),
+        "mean_radius_minus_fit": {"max_abs": float(np.abs(dR).max()), "rms": float(np.sqrt((dR ** 2).mean()))},
+        "asymmetry_minus_fit": {"max_abs": float(np.abs(dA).max()), "rms": float(np.sqrt((dA ** 2).mean()))},
+        "edge_on": [{"a": r.a, "D": r.measures["D"], "R_mean": r.measures["R_mean"], "A": r.measures["A"]}
+                    for r in edge_on],
+    })
+    return timing
+
+
 def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
     """Time `steps` passes (camera_init + integrate + classify) after `warmup`."""
     params = W.Params(precision=prec)
@@ -315,6 +337,9 @@ def main():
     if not args.no_sweep:
         print("bench: 256-camera sweep", file=sys.stderr, flush=True)
         out["sweep"] = sweep(G, W, torch, np)
+    if not args.no_ring:
+        print("bench: photon-ring study", file=sys.stderr, flush=True)
+        out["ring_study"] = ring_study(np)
     if not args.no_serve:
         print("bench: serving", file=sys.stderr, flush=True)
         out["serving"] = serving(args)

@@ -106,22 +106,37 @@ typedef enum {
                                camera are ignored by camera_init and classify
                                and must not be GRAY_RUNNING for integrate.   */
 
+/* gray_camera.kind */
+typedef enum {
+    GRAY_CAMERA_GRID = 0,  /* cell-centred Cartesian grid in (alpha, beta)        */
+    GRAY_CAMERA_POLAR = 1  /* polar grid (R, vartheta) about the image centre, as
+                              in the photon-ring study of Sec. 4                 */
+} gray_camera_kind;
+
 /* One camera: a Kerr hole of spin a seen from distance r_obs at inclination
- * incl (radians from the spin axis, azimuth 0), with a regular cell-centred
- * nx * ny grid on a flat image plane perpendicular to the line of sight
- * (Sec. 2 and Sec. 3 place the image plane at r = 1000 M). Pixel (ix, iy) has
- *   alpha = alpha_lo + (alpha_hi - alpha_lo) (ix + 1/2) / nx   (along +phi)
- *   beta  = beta_lo  + (beta_hi  - beta_lo)  (iy + 1/2) / ny   (towards the
- *           spin axis)
- * and is photon  first + iy * nx + ix.  Constraints: 0 <= a < 1,
- * r_obs > r_bh = 1 + sqrt(1 - a^2), 0 <= incl <= pi, nx, ny >= 1, finite
- * ranges. Cameras passed together must tile [0, n) in order with no gaps
- * (unless GRAY_SLOTS is set). */
+ * incl (radians from the spin axis, azimuth 0), with a regular nx * ny grid
+ * on a flat image plane perpendicular to the line of sight (Sec. 2 and Sec. 3
+ * place the image plane at r = 1000 M). Pixel (ix, iy) is photon
+ * first + iy * nx + ix and has image-plane coordinates (alpha along +phi,
+ * beta towards the spin axis)
+ *   GRAY_CAMERA_GRID:
+ *     alpha = alpha_lo + (alpha_hi - alpha_lo) (ix + 1/2) / nx
+ *     beta  = beta_lo  + (beta_hi  - beta_lo)  (iy + 1/2) / ny
+ *   GRAY_CAMERA_POLAR (alpha_* bound the radius R, beta_* the angle):
+ *     R = alpha_lo + (alpha_hi - alpha_lo) (ix + 1/2) / nx
+ *     vartheta = beta_lo + (beta_hi - beta_lo) iy / (ny - 1)  (beta_lo if ny = 1)
+ *     alpha = R cos(vartheta),  beta = R sin(vartheta)
+ * Constraints: 0 <= a < 1, r_obs > r_bh = 1 + sqrt(1 - a^2), 0 <= incl <= pi,
+ * nx, ny >= 1, finite ranges, kind one of gray_camera_kind. Cameras passed
+ * together must tile [0, n) in order with no gaps (unless GRAY_SLOTS is
+ * set). */
 typedef struct {
     double a, r_obs, incl;
     int32_t nx, ny;
     double alpha_lo, alpha_hi, beta_lo, beta_hi;
     int64_t first;
+    int32_t kind;      /* gray_camera_kind */
+    int32_t reserved;  /* 0 */
 } gray_camera;
 
 /* Integrator parameters (Sec. 2 names them Delta, delta and epsilon). */

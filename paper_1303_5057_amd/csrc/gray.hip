@@ -81,7 +81,7 @@ static_assert(sizeof(DevCam) == 64, "DevCam is one 64-byte record");
 struct CamArg {
     double a, r_obs, incl, alo, ahi, blo, bhi;
     int64_t first;
-    int32_t nx, ny, index, pad;
+    int32_t nx, ny, index, kind;
 };
 struct CamChunk {
     CamArg c[kCamChunk];
@@ -115,13 +115,23 @@ __device__ __forceinline__ int find_camera(const CamChunk &ch, int64_t i)
     return k;
 }
 
+// Image-plane coordinates of photon i of camera c (see gray_camera).
 __device__ __forceinline__ void pixel_of(const CamArg &c, int64_t i, double &alpha, double &beta)
 {
     const int64_t local = i - c.first;
     const int32_t iy = (int32_t)(local / c.nx);
     const int32_t ix = (int32_t)(local - (int64_t)iy * c.nx);
-    alpha = c.alo + (c.ahi - c.alo) * ((ix + 0.5) / c.nx);
-    beta = c.blo + (c.bhi - c.blo) * ((iy + 0.5) / c.ny);
+    const double u = c.alo + (c.ahi - c.alo) * ((ix + 0.5) / c.nx);
+    if (c.kind == GRAY_CAMERA_POLAR) {
+        const double th = c.ny > 1 ? c.blo + (c.bhi - c.blo) * ((double)iy / (c.ny - 1)) : c.blo;
+        double s, co;
+        sincos(th, &s, &co);
+        alpha = u * co;
+        beta = u * s;
+    } else {
+        alpha = u;
+        beta = c.blo + (c.bhi - c.blo) * ((iy + 0.5) / c.ny);
+    }
 }
 
 // ------------------------------------------------------- camera initialisation
@@ -831,6 +841,7 @@ static int validate_params(const gray_params *p)
 
 static bool camera_physical_ok(const gray_camera &c)
 {
+    if (c.kind != GRAY_CAMERA_GRID && c.kind != GRAY_CAMERA_POLAR) return false;
     if (!(c.a >= 0.0 && c.a < 1.0)) return false;
     if (!(c.r_obs > horizon_radius(c.a) && std::isfinite(c.r_obs))) return false;
     if (!(c.incl >= 0.0 && c.incl <= kPi)) return false;
@@ -911,6 +922,7 @@ static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool sl
         o.nx = c.nx;
         o.ny = c.ny;
         o.index = k0 + j;
+        o.kind = c.kind;
         lo = std::min(lo, c.first);
         hi = std::max(hi, c.first + m);
     }
@@ -1219,7 +1231,7 @@ extern "C" const char *gray_strerror(int code)
     }
 }
 
-extern "C" int gray_version(void) { return 101; }
+extern "C" int gray_version(void) { return 102; }
 
 extern "C" size_t gray_struct_size(int which)
 {

@@ -32,12 +32,17 @@ GRAY_WORKLIST_SLACK = 1 << 20
 PRECISIONS = {"fp64": GRAY_FP64, "fp32c": GRAY_FP32C}
 
 
+# gray_camera.kind
+GRAY_CAMERA_GRID = 0
+GRAY_CAMERA_POLAR = 1
+
+
 class gray_camera(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("r_obs", ctypes.c_double), ("incl", ctypes.c_double),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("alpha_lo", ctypes.c_double), ("alpha_hi", ctypes.c_double),
                 ("beta_lo", ctypes.c_double), ("beta_hi", ctypes.c_double),
-                ("first", ctypes.c_int64)]
+                ("first", ctypes.c_int64), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gray_params(ctypes.Structure):
@@ -159,7 +164,7 @@ def camera_array(cams: Sequence[Camera]):
     first = 0
     for k, c in enumerate(cams):
         arr[k] = gray_camera(c.a, c.r_obs, c.incl, c.nx, c.ny, c.alpha_lo, c.alpha_hi, c.beta_lo,
-                             c.beta_hi, first)
+                             c.beta_hi, first, c.kind, 0)
         first += c.nx * c.ny
     return arr
 

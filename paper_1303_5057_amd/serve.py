@@ -182,7 +182,7 @@ class Server:
             return False
         k = free_slots[0]
         self.slots[k] = G.gray_camera(c.a, c.r_obs, c.incl, c.nx, c.ny, c.alpha_lo, c.alpha_hi,
-                                      c.beta_lo, c.beta_hi, first)
+                                      c.beta_lo, c.beta_hi, first, c.kind, 0)
         G.gray_camera_init_slot(self.slots, self.max_slots, k, self.p, self.state, self.stream)
         res = RequestResult(req.rid, req.arrival_s, admit_s=now, photons=n)
         self.active[k] = (req, first, n, res)

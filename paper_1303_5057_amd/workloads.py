@@ -23,7 +23,10 @@ SEED_BASE = 20260000
 @dataclass(frozen=True)
 class Camera:
     """Kerr spin a, observer distance r_obs (M), inclination incl (radians),
-    and a cell-centred nx x ny grid over [alpha_lo, alpha_hi] x [beta_lo, beta_hi] (M)."""
+    and an nx x ny image-plane grid: kind 0, cell-centred over
+    [alpha_lo, alpha_hi] x [beta_lo, beta_hi] (M); kind 1 (polar), nx
+    cell-centred radii in [alpha_lo, alpha_hi] times ny angles from beta_lo
+    to beta_hi inclusive (radians)."""
     a: float
     r_obs: float
     incl: float
@@ -33,6 +36,7 @@ class Camera:
     alpha_hi: float
     beta_lo: float
     beta_hi: float
+    kind: int = 0
 
     @property
     def n(self) -> int:

@@ -42,7 +42,7 @@ def test_struct_layouts(lib):
     for k, t in enumerate((G.gray_camera, G.gray_params, G.gray_state, G.gray_result)):
         assert lib.gray_struct_size(k) == ctypes.sizeof(t)
     assert lib.gray_struct_size(99) == 0
-    assert ctypes.sizeof(G.gray_camera) == 72
+    assert ctypes.sizeof(G.gray_camera) == 80
 
 
 def test_strerror_and_version(lib):
@@ -96,6 +96,7 @@ def test_invalid_params_rejected(lib, field, value):
     W.Camera(0.5, 1.5, 1.0, 8, 8, -5, 5, -5, 5),          # observer inside the horizon
     W.Camera(0.5, 1000.0, 3.5, 8, 8, -5, 5, -5, 5),       # inclination > pi
     W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, math.nan, -5, 5),
+    W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, kind=2),             # unknown camera kind
 ])
 def test_invalid_camera_rejected(lib, cam):
     p = G.params_struct(W.Params())

@@ -1,0 +1,124 @@
+"""Pins of the photon-ring oracle (oracle/ring.py, Sec. 4) on the CPU.
+
+* The ring measures D, <R>, A against closed forms: a circle about the image
+  centre, a circle displaced along alpha (its displacement is D, its radius
+  <R>, A = 0) and an ellipse, whose <R> and A are one-dimensional integrals
+  evaluated here by adaptive quadrature.
+* The paper's fits reduce to the Schwarzschild ring (<R> = sqrt(27) M to
+  within the fit's rounding, A = 0) at a = 0.
+* The oracle's edge (the number of captured rays along an angle, found by
+  bisection with full FP64 traces) equals the exact count from the Kerr
+  radial potential (a ray of the grid is captured iff R(r) has no turning
+  point between the horizon and the observer), except within 5 deg of the
+  beta axis, where rays with L_z ~ 0 cross the polar axis next to the
+  critical curve and the scheme's own error moves the edge by <= 3 rays.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import analytic
+from oracle import ring as R
+
+THETAS = np.linspace(0.0, math.pi, 181)
+
+
+def test_measures_centred_circle():
+    m = R.measures(THETAS, np.full(181, 4.25))
+    assert m["D"] == pytest.approx(0.0, abs=1e-14)
+    assert m["R_mean"] == pytest.approx(4.25, rel=1e-14)
+    assert m["A"] == pytest.approx(0.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("shift", [0.37, -1.2])
+def test_measures_displaced_circle(shift):
+    rho = 5.0
+    # polar radius about the image centre of the circle |z - shift| = rho
+    r = shift * np.cos(THETAS) + np.sqrt(rho * rho - (shift * np.sin(THETAS)) ** 2)
+    m = R.measures(THETAS, r)
+    assert m["D"] == pytest.approx(abs(shift), rel=1e-12)
+    assert m["center"] == pytest.approx(shift, rel=1e-12)
+    assert m["R_mean"] == pytest.approx(rho, rel=1e-12)
+    assert m["A"] == pytest.approx(0.0, abs=1e-10)
+
+
+def test_measures_ellipse_against_quadrature():
+    p, q = 5.4, 4.9      # semi-axes along alpha and beta
+
+    def rad(t):
+        return p * q / math.sqrt((q * math.cos(t)) ** 2 + (p * math.sin(t)) ** 2)
+
+    mean = integrate.quad(rad, 0.0, 2.0 * math.pi, epsabs=1e-13)[0] / (2.0 * math.pi)
+    var = integrate.quad(lambda t: (rad(t) - mean) ** 2, 0.0, 2.0 * math.pi, epsabs=1e-14)[0] / (2.0 * math.pi)
+    m = R.measures(THETAS, np.array([rad(t) for t in THETAS]))
+    assert m["D"] == pytest.approx(0.0, abs=1e-12)
+    assert m["R_mean"] == pytest.approx(mean, rel=1e-10)
+    assert m["A"] == pytest.approx(2.0 * math.sqrt(var), rel=1e-8)
+
+
+def test_fits_reduce_to_schwarzschild():
+    # R0(0) = 5.2 is sqrt(27) rounded (3.8e-3) and |R1(0)| = 3.5e-3
+    for i in range(0, 91, 5):
+        assert abs(R.fit_mean_radius(0.0, i) - math.sqrt(27.0)) < 8e-3
+        assert R.fit_asymmetry(0.0, i) == 0.0
+    # the fitted asymmetry grows with spin and vanishes face-on
+    assert R.fit_asymmetry(0.99, 0) == 0.0
+    assert 0 < R.fit_asymmetry(0.5, 60) < R.fit_asymmetry(0.9, 60) < R.fit_asymmetry(0.99, 60)
+
+
+def _exact_counts(orc, a, incl, thetas, nr, r_lo, r_hi, r_obs=1000.0):
+    """Captured rays per angle from the radial potential (bisection over the
+    ray index; the captured set along an angle is the inner segment)."""
+    out = []
+    for t in thetas:
+        def cap(k):
+            rad = r_lo + (r_hi - r_lo) * (k + 0.5) / nr
+            x = orc.camera(a, r_obs, incl, rad * math.cos(t), rad * math.sin(t))
+            E, L, Q = orc.conserved(a, x)
+            return analytic.captured_by_potential(a, L / E, Q / E ** 2, x[1])
+        lo, hi = 0, nr
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if cap(mid):
+                lo = mid + 1
+            else:
+                hi = mid
+        out.append(lo)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("a,incl_deg", [(0.0, 60.0), (0.9, 60.0), (0.99, 90.0), (0.6, 0.0)])
+def test_oracle_edge_equals_radial_potential(orc, a, incl_deg):
+    thetas = np.linspace(0.0, math.pi, 7)
+    nr, r_lo, r_hi = 6000, 1.5, 7.5
+    incl = math.radians(incl_deg)
+    got = R.edge_counts(a, 1000.0, incl, thetas, nr, r_lo, r_hi)
+    want = _exact_counts(orc, a, incl, thetas, nr, r_lo, r_hi)
+    # Along the beta axis (alpha ~ 0, so L_z ~ 0) the edge rays cross the
+    # polar axis next to the critical curve; the scheme's pole treatment
+    # locks them into h/9 Euler steps with Q drifting by ~10%, which moves
+    # the integrator's edge by a few rays there (0.9, 60 deg: 2 rays).
+    polar = np.abs(np.cos(thetas)) < math.sin(math.radians(5.0))
+    assert np.array_equal(got[~polar], want[~polar]), (got, want)
+    assert np.all(np.abs(got[polar] - want[polar]) <= 3), (got, want)
+    if a == 0.0:
+        # the Schwarzschild edge is the sqrt(27) circle, to the grid spacing
+        # and the flat-screen distortion at r = 1000 M
+        radius = r_lo + got * (r_hi - r_lo) / nr
+        assert np.all(np.abs(radius - math.sqrt(27.0)) < 1e-2)
+
+
+def test_oracle_edge_is_a_boundary(orc):
+    """Along an angle the captured rays are exactly the first N: the rays
+    just inside and outside the bisection's edge, and a sparse sample of the
+    rest, are classified accordingly by the oracle."""
+    a, incl = 0.9, math.radians(75.0)
+    nr, r_lo, r_hi = 6000, 1.5, 7.5
+    for t in (0.3, 1.6, 2.9):
+        n = int(R.edge_counts(a, 1000.0, incl, [t], nr, r_lo, r_hi)[0])
+        idx = np.unique(np.concatenate([np.arange(0, nr, 301), [n - 2, n - 1, n, n + 1]]))
+        st = R.ray_status(a, 1000.0, incl, t, idx, nr, r_lo, r_hi)
+        assert np.all(st[idx < n] == orc.CAPTURED)
+        assert np.all(st[idx >= n] == orc.ESCAPED)
