@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
     ap.add_argument("--no-ring", action="store_true", help="skip the photon-ring study")
+    ap.add_argument("--no-nsweep", action="store_true",
+                    help="skip the grid-projection run time versus number of rays")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 256 MiB (read 256 MiB, write "
                          "256 MiB), the reference for the HBM traffic counters")
@@ -194,6 +196,39 @@ def cpu_baseline(cam, params, every: int):
             "per_core_ns_per_photon_step": dt * 1e9 / nsteps * threads,
             "single_thread_64x64_schwarzschild_ns_per_photon_step": dt1 * 1e9 / int(r1.steps.sum()),
             "nproc": os.cpu_count(), "cpu_model": model}
+
+
+def projection_nsweep(G, W, torch, np) -> dict:
+    """The paper's first benchmark (Sec. 3): run time of the grid projection
+    (a = 0.95, i = 60 deg, recorder on, FP64) against the number of rays n,
+    from 8 x 8 to 4096 x 4096: the integrate call and the whole pass
+    (camera_init + integrate + classify), medians of HIP-event timings."""
+    rows = []
+    for side in (8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
+        cam = W.projection_camera(0.95, 60.0, side)
+        b = G.Batch([cam], W.PROJECTION_PARAMS, counters=False, mark=False)
+        reps = 7 if side <= 1024 else 3
+        t_int, t_pass = [], []
+        for rep in range(reps + 1):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            b.camera_init()
+            ev[1].record()
+            b.integrate()
+            ev[2].record()
+            b.classify(xf=False, cons=False, counts=True)
+            ev[3].record()
+            torch.cuda.synchronize()
+            if rep:
+                t_int.append(ev[1].elapsed_time(ev[2]))
+                t_pass.append(ev[0].elapsed_time(ev[3]))
+        steps = int(b.steps[: b.n].to(torch.int64).sum().item())
+        hit = float((b.disk.view(3, b.stride)[0, : b.n] > 0).float().mean().item())
+        ti, tp = float(np.median(t_int)), float(np.median(t_pass))
+        rows.append({"side": side, "n": b.n, "integrate_ms": ti, "pass_ms": tp, "photon_steps": steps,
+                     "ns_per_photon_step": ti * 1e6 / steps, "crossed_fraction": hit})
+        del b
+    return {"workload": "grid projection a=0.95 i=60deg, window +-12 M, FP64", "rows": rows}
 
 
 def ring_study(np) -> dict:
@@ -337,6 +372,9 @@ def main():
     if not args.no_sweep:
         print("bench: 256-camera sweep", file=sys.stderr, flush=True)
         out["sweep"] = sweep(G, W, torch, np)
+    if not args.no_nsweep:
+        print("bench: grid-projection n-sweep", file=sys.stderr, flush=True)
+        out["projection_nsweep"] = projection_nsweep(G, W, torch, np)
     if not args.no_ring:
         print("bench: photon-ring study", file=sys.stderr, flush=True)
         out["ring_study"] = ring_study(np)

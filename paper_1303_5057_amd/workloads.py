@@ -80,6 +80,21 @@ C2 = Camera(0.99, 1000.0, deg(90.0), 512, 512, -8.0, 8.0, -8.0, 8.0)
 C3 = Camera(0.9375, 1000.0, deg(17.0), 4096, 4096, -12.0, 12.0, -12.0, 12.0)
 C3_PARAMS = Params(record_disk=True, disk_rmin=-1.0, disk_rmax=50.0, precision="fp32c")
 
+# Grid projection (Sec. 3): a uniform Cartesian image-plane grid projected
+# onto the equatorial plane (first crossing at any radius, recorder window
+# [0, 1000] M) for spins 0 and 0.95 at inclinations 0 and 60 deg; the
+# a = 0.95, i = 60 deg case is the paper's run-time-versus-n benchmark.
+PROJECTION_CONFIGS = ((0.0, 0.0), (0.0, 60.0), (0.95, 0.0), (0.95, 60.0))
+PROJECTION_HALF_WIDTH = 12.0
+PROJECTION_PARAMS = Params(record_disk=True, disk_rmin=0.0, disk_rmax=1000.0)
+
+
+def projection_camera(a: float, incl_deg: float, side: int,
+                      half_width: float = PROJECTION_HALF_WIDTH) -> Camera:
+    return Camera(a, 1000.0, deg(incl_deg), side, side, -half_width, half_width, -half_width,
+                  half_width)
+
+
 # The paper's pole test (Sec. 2): a = 0.99, r0 cos(theta0) = 1000 M,
 # r0 sin(theta0) = 4.833605 M, phi0 = 0. With the observer on the axis
 # (incl = 0) the screen point (alpha, beta) = (0, -4.833605) has exactly
