@@ -231,6 +231,35 @@ def projection_nsweep(G, W, torch, np) -> dict:
     return {"workload": "grid projection a=0.95 i=60deg, window +-12 M, FP64", "rows": rows}
 
 
+def pole_ablation(G, W, torch, np) -> dict:
+    """The paper's pole case (a = 0.99, r0 sin(theta0) = 4.833605 M) rotated
+    to phi0 = 0..359 deg under the three treatments of the polar axis
+    (Sec. 2, Fig. 2), FP64: outcome, step counts and the drift of E, L_z, Q
+    at the last state with r >= 2 r_bh."""
+    import math
+    cams = [W.pole_camera(math.radians(d)) for d in range(360)]
+    out = {}
+    for name, mode in (("production_monitor", G.GRAY_POLE_MONITOR),
+                       ("euler_on_crossing", G.GRAY_POLE_EULER_CROSSING),
+                       ("none", G.GRAY_POLE_NONE)):
+        b = G.Batch(cams, W.Params(pole_mode=mode))
+        res = b.run()
+        torch.cuda.synchronize()
+        n = b.n
+        status = b.status[:n].cpu().numpy()
+        steps = b.steps[:n].cpu().numpy()
+        ctr = b.counters.view(3, b.stride)[:, :n].cpu().numpy()
+        drift = res.cons.view(9, b.stride)[6:9, :n].cpu().numpy()
+        out[name] = {"status_counts": np.bincount(status, minlength=5).tolist(),
+                     "steps_median": float(np.median(steps)), "steps_max": int(steps.max()),
+                     "euler_steps_median": float(np.median(ctr[0])),
+                     "remaps_median": float(np.median(ctr[1])),
+                     "drift_ELQ_median": np.median(drift, axis=1).tolist(),
+                     "drift_ELQ_max": drift.max(axis=1).tolist()}
+        del b, res
+    return out
+
+
 def ring_study(np) -> dict:
     """The photon-ring parameter study (16 spins x 19 inclinations, 6000 x 181
     polar rays each, 3.3e8 rays) in one persistent launch: integrate time,
@@ -332,7 +361,8 @@ def main():
     total_steps = head["total_steps"]
     achieved = F_STEP[args.precision] * total_steps / (head["integrate_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    kernel = "k_integrate<GRAY_FP64>" if args.precision == "fp64" else "k_integrate<GRAY_FP32C>"
+    kernel = ("k_integrate<GRAY_FP64, kPoleMonitor>" if args.precision == "fp64"
+              else "k_integrate<GRAY_FP32C, kPoleMonitor>")
     out = {
         "metric": "ns/photon/step",
         "value": head["ms_per_step"] * 1e6 / total_steps,
@@ -375,6 +405,8 @@ def main():
     if not args.no_nsweep:
         print("bench: grid-projection n-sweep", file=sys.stderr, flush=True)
         out["projection_nsweep"] = projection_nsweep(G, W, torch, np)
+    print("bench: pole-treatment ablation", file=sys.stderr, flush=True)
+    out["pole_ablation"] = pole_ablation(G, W, torch, np)
     if not args.no_ring:
         print("bench: photon-ring study", file=sys.stderr, flush=True)
         out["ring_study"] = ring_study(np)

@@ -139,6 +139,20 @@ typedef struct {
     int32_t reserved;  /* 0 */
 } gray_camera;
 
+/* Treatment of steps near the polar axis, where Boyer-Lindquist coordinates
+ * are singular (Sec. 2, Fig. 2). The production scheme is the default; the
+ * other two are the paper's earlier treatments, kept for comparison. */
+typedef enum {
+    GRAY_POLE_MONITOR = 0,        /* production: when the RK4 step violates the
+                                     null condition eq. (4) by more than xi_eps,
+                                     re-integrate it with one forward-Euler step
+                                     of h / euler_div                          */
+    GRAY_POLE_EULER_CROSSING = 1, /* when the RK4 step ends across a pole
+                                     (theta outside [0, pi]), replace it by one
+                                     forward-Euler step of the same h          */
+    GRAY_POLE_NONE = 2            /* RK4 and the remap of eq. (3) only          */
+} gray_pole_mode;
+
 /* Integrator parameters (Sec. 2 names them Delta, delta and epsilon). */
 typedef struct {
     double step_frac;    /* Delta of the step-size rule eq. (2); ~1/32      > 0 */
@@ -160,6 +174,9 @@ typedef struct {
                             0: run to termination                                */
     int32_t precision;   /* gray_precision                                       */
     uint32_t flags;      /* GRAY_RECORD_DISK                                     */
+    int32_t pole_mode;   /* gray_pole_mode; GRAY_FP32C supports GRAY_POLE_MONITOR
+                            only (GRAY_EUNSUPPORTED otherwise)                  */
+    int32_t reserved;    /* 0                                                    */
 } gray_params;
 
 typedef struct {

@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("r_escape", ctypes.c_double), ("xi_eps", ctypes.c_double),
                 ("euler_div", ctypes.c_double), ("disk_rmin", ctypes.c_double),
                 ("disk_rmax", ctypes.c_double), ("max_steps", ctypes.c_int32),
-                ("record_disk", ctypes.c_int32)]
+                ("record_disk", ctypes.c_int32), ("pole_mode", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class CameraT(ctypes.Structure):
@@ -53,11 +54,14 @@ class CameraT(ctypes.Structure):
                 ("beta_lo", ctypes.c_double), ("beta_hi", ctypes.c_double)]
 
 
+POLE_MONITOR, POLE_EULER_CROSSING, POLE_NONE = 0, 1, 2
+
+
 def make_params(step_frac=1.0 / 32, horizon_eps=1e-3, r_escape=1000.0, xi_eps=1e-3,
                 euler_div=9.0, max_steps=65536, record_disk=False, disk_rmin=-1.0,
-                disk_rmax=50.0) -> Params:
+                disk_rmax=50.0, pole_mode=POLE_MONITOR) -> Params:
     return Params(step_frac, horizon_eps, r_escape, xi_eps, euler_div, disk_rmin, disk_rmax,
-                  int(max_steps), 1 if record_disk else 0)
+                  int(max_steps), 1 if record_disk else 0, int(pole_mode), 0)
 
 
 _lib = None

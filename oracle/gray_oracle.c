@@ -288,11 +288,22 @@ int oracle_step(const oracle_params *p, double a, double x[8], double *h_used)
         xn[i] = x[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
 
     int flags = 0;
-    double xi = oracle_xi(a, xn);
-    if (fabs(xi + 1.0) > p->xi_eps) {
-        double he = h / p->euler_div;
-        for (int i = 0; i < 8; ++i) xn[i] = x[i] + he * k1[i];
-        flags |= 1;
+    if (p->pole_mode == 0) {
+        /* production scheme: re-integrate with Euler at h / euler_div when
+         * the step violates the null condition, eq. (4) */
+        double xi = oracle_xi(a, xn);
+        if (fabs(xi + 1.0) > p->xi_eps) {
+            double he = h / p->euler_div;
+            for (int i = 0; i < 8; ++i) xn[i] = x[i] + he * k1[i];
+            flags |= 1;
+        }
+    } else if (p->pole_mode == 1) {
+        /* earlier scheme: a step whose end lies across a pole is replaced by
+         * a forward Euler step of the same size */
+        if (xn[2] < 0.0 || xn[2] > ORACLE_PI) {
+            for (int i = 0; i < 8; ++i) xn[i] = x[i] + h * k1[i];
+            flags |= 1;
+        }
     }
     if (oracle_remap(xn)) flags |= 2;
     memcpy(x, xn, sizeof xn);

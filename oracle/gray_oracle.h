@@ -34,6 +34,12 @@ typedef struct {
     double disk_rmax;
     int32_t max_steps;  /* total accepted steps before UNFINISHED                 */
     int32_t record_disk;/* nonzero: record the first in-window equatorial crossing */
+    int32_t pole_mode;  /* treatment of the polar axis (Sec. 2, Fig. 2):
+                           0 production: null monitor eq. (4), Euler at h/euler_div;
+                           1 earlier scheme: one Euler step of the same h whenever
+                             the RK4 step crosses a pole;
+                           2 none: RK4 and the remap of eq. (3) only             */
+    int32_t pad;
 } oracle_params;
 
 typedef struct {

@@ -31,6 +31,10 @@
 
 namespace gray {
 
+static_assert(kPoleMonitor == GRAY_POLE_MONITOR && kPoleEulerCrossing == GRAY_POLE_EULER_CROSSING &&
+                  kPoleNone == GRAY_POLE_NONE,
+              "pole treatments match gray_pole_mode");
+
 // ------------------------------------------------------------------ errors
 static thread_local char g_last_error[512] = "no device error";
 
@@ -458,8 +462,11 @@ __device__ __forceinline__ bool finite_state(const State<double> &x)
 // current 64-photon chunk, taking a new chunk from the global counter when the
 // old one is used up. A wave exits once the counter is past n and all its
 // lanes are idle; every photon ends within max_steps (or call_steps) steps,
-// so every wave exits.
-template <int P>
+// so every wave exits. PM is the treatment of the polar axis (FP64 only;
+// the production monitor unless a caller asks for one of the paper's
+// earlier treatments), a template parameter so that the production kernel
+// carries no code for the others.
+template <int P, int PM = kPoleMonitor>
 __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
     const unsigned lane = threadIdx.x & (kWave - 1);
@@ -583,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
             State<double> x;
             int fl;
             if constexpr (P == GRAY_FP64) {
-                fl = rk4_step(K, L.x, L.s, L.c);
+                fl = rk4_step<PM>(K, L.x, L.s, L.c);
                 x = L.x;
             } else {
                 auto &F = L;
@@ -833,6 +840,10 @@ static int validate_params(const gray_params *p)
     if (!(p->fp64_horizon >= 0.0 && std::isfinite(p->fp64_horizon))) return GRAY_EINVAL;
     if (!(p->fp64_pole >= 0.0 && std::isfinite(p->fp64_pole))) return GRAY_EINVAL;
     if (!(p->fp64_turn >= 0.0 && std::isfinite(p->fp64_turn))) return GRAY_EINVAL;
+    if (p->pole_mode != GRAY_POLE_MONITOR && p->pole_mode != GRAY_POLE_EULER_CROSSING &&
+        p->pole_mode != GRAY_POLE_NONE)
+        return GRAY_EINVAL;
+    if (p->precision == GRAY_FP32C && p->pole_mode != GRAY_POLE_MONITOR) return GRAY_EUNSUPPORTED;
     if (p->flags & GRAY_RECORD_DISK) {
         if (!(p->disk_rmax > 0.0) || std::isnan(p->disk_rmin)) return GRAY_EINVAL;
     }
@@ -931,9 +942,17 @@ static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool sl
     return ch.count > 0;
 }
 
+// Integrator variants: FP64 with each pole treatment, FP32C (production
+// treatment only).
+constexpr int kVariants = 4;
+static int variant_of(const gray_params *p)
+{
+    return p->precision == GRAY_FP32C ? 1 : (p->pole_mode == GRAY_POLE_MONITOR ? 0 : 1 + p->pole_mode);
+}
+
 struct DeviceInfo {
     int cus = 0;
-    int blocks_per_cu[2] = {0, 0};
+    int blocks_per_cu[kVariants] = {0, 0, 0, 0};
 };
 static std::mutex g_dev_mutex;
 static DeviceInfo g_dev[64];
@@ -950,13 +969,15 @@ static int device_info(DeviceInfo &out)
         int cus = 0;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
-        int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<GRAY_FP64>, kBlock, 0);
-        if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-        d.blocks_per_cu[GRAY_FP64] = nb > 0 ? nb : 1;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_integrate<GRAY_FP32C>, kBlock, 0);
-        if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-        d.blocks_per_cu[GRAY_FP32C] = nb > 0 ? nb : 1;
+        const void *kernels[kVariants] = {
+            (const void *)k_integrate<GRAY_FP64, kPoleMonitor>, (const void *)k_integrate<GRAY_FP32C, kPoleMonitor>,
+            (const void *)k_integrate<GRAY_FP64, kPoleEulerCrossing>, (const void *)k_integrate<GRAY_FP64, kPoleNone>};
+        for (int v = 0; v < kVariants; ++v) {
+            int nb = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[v], kBlock, 0);
+            if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+            d.blocks_per_cu[v] = nb > 0 ? nb : 1;
+        }
         d.cus = cus;
     }
     out = d;
@@ -1158,15 +1179,18 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.call_steps = p->call_steps;
     A.flags = p->flags;
     A.refill = 1;
-    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[p->precision];
+    const int variant = variant_of(p);
+    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[variant];
     // In work-list mode the list length is only known on the device; the grid
     // is capped at kMaxListWaves waves, which bounds the unused list tail.
     const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave)) : blocks_for(s->n);
     const unsigned grid = (unsigned)(need < resident ? need : resident);
-    if (p->precision == GRAY_FP64)
-        hipLaunchKernelGGL(k_integrate<GRAY_FP64>, dim3(grid), dim3(kBlock), 0, st, A);
-    else
-        hipLaunchKernelGGL(k_integrate<GRAY_FP32C>, dim3(grid), dim3(kBlock), 0, st, A);
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 1: hipLaunchKernelGGL((k_integrate<GRAY_FP32C, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 2: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleEulerCrossing>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    default: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    }
     return check_launch("integrate launch");
 }
 
@@ -1231,7 +1255,7 @@ extern "C" const char *gray_strerror(int code)
     }
 }
 
-extern "C" int gray_version(void) { return 102; }
+extern "C" int gray_version(void) { return 103; }
 
 extern "C" size_t gray_struct_size(int which)
 {

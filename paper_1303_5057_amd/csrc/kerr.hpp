@@ -379,6 +379,10 @@ GRAY_HD bool xi_violated(const Metric<T> &g, T kt, T kr, T kth, T kph, T eps)
     return fabs(num + den) > eps * fabs(den);
 }
 
+// Treatment of the polar axis (values of gray_pole_mode): the production
+// null-condition monitor, the earlier Euler step on pole crossings, or none.
+constexpr int kPoleMonitor = 0, kPoleEulerCrossing = 1, kPoleNone = 2;
+
 // Integrator constants of one photon.
 template <class T>
 struct StepConst {
@@ -389,11 +393,14 @@ struct StepConst {
 // One accepted step of the production scheme (Sec. 2): classical RK4 with h
 // from eq. (2); if the proposal violates the null condition, |xi + 1| > eps
 // (eq. 4), one forward-Euler step of h / euler_div from the same start
-// replaces it; then the remap of eq. (3). (s, c) = sin/cos(x.th) on entry and
+// replaces it; then the remap of eq. (3). PM selects the paper's earlier
+// treatments instead: kPoleEulerCrossing replaces a step that ends across a
+// pole by one forward-Euler step of the same h; kPoleNone keeps every RK4
+// step. (s, c) = sin/cos(x.th) on entry and
 // on exit (always recomputed from the final theta, so a step is a function of
 // the stored state alone). Returns bit 0 = Euler fallback, bit 1 = remap, or
 // -1 when h is not a positive finite number (state kept).
-template <class T>
+template <int PM = kPoleMonitor, class T>
 GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
 {
     // eq. (2): h1 = Delta r / D1 with D1 = |k^r| + r (|k^th| + |k^ph|), and
@@ -430,10 +437,17 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
 
     int flags = 0;
     sin_cos(xn.th, sy, cy);
-    const Metric<T> g = metric(K.B.a, K.B.a2, xn.r, sy, cy);
-    if (xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps)) {
-        xn = axpy(x, quot(h, K.euler_div), k1);
-        flags |= 1;
+    if constexpr (PM == kPoleMonitor) {
+        const Metric<T> g = metric(K.B.a, K.B.a2, xn.r, sy, cy);
+        if (xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps)) {
+            xn = axpy(x, quot(h, K.euler_div), k1);
+            flags |= 1;
+        }
+    } else if constexpr (PM == kPoleEulerCrossing) {
+        if (xn.th > T(kPi) || xn.th < T(0)) {
+            xn = axpy(x, h, k1);
+            flags |= 1;
+        }
     }
     if (xn.th > T(kPi)) {
         xn.th = T(kTwoPi) - xn.th;

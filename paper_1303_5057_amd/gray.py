@@ -32,6 +32,9 @@ GRAY_WORKLIST_SLACK = 1 << 20
 PRECISIONS = {"fp64": GRAY_FP64, "fp32c": GRAY_FP32C}
 
 
+# gray_params.pole_mode
+GRAY_POLE_MONITOR, GRAY_POLE_EULER_CROSSING, GRAY_POLE_NONE = 0, 1, 2
+
 # gray_camera.kind
 GRAY_CAMERA_GRID = 0
 GRAY_CAMERA_POLAR = 1
@@ -53,7 +56,8 @@ class gray_params(ctypes.Structure):
                 ("fp64_pole", ctypes.c_double), ("fp64_turn", ctypes.c_double),
                 ("max_steps", ctypes.c_int32),
                 ("call_steps", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("pole_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class gray_state(ctypes.Structure):
@@ -173,7 +177,7 @@ def params_struct(p: Params) -> gray_params:
     return gray_params(p.step_frac, p.horizon_eps, p.r_escape, p.xi_eps, p.euler_div, p.disk_rmin,
                        p.disk_rmax, p.fp64_horizon, p.fp64_pole, p.fp64_turn, p.max_steps,
                        p.call_steps, PRECISIONS[p.precision],
-                       GRAY_RECORD_DISK if p.record_disk else 0)
+                       GRAY_RECORD_DISK if p.record_disk else 0, p.pole_mode, 0)
 
 
 def _ptr(t) -> Optional[int]:

@@ -65,6 +65,9 @@ class Params:
     fp64_horizon: float = 1.0
     fp64_pole: float = 0.05
     fp64_turn: float = 0.01
+    # treatment of the polar axis (Sec. 2): 0 the production null-condition
+    # monitor, 1 the earlier Euler step on pole crossings, 2 none
+    pole_mode: int = 0
 
 
 def deg(x: float) -> float:

@@ -46,7 +46,7 @@ def oracle_params(p: W.Params):
     return oracle.make_params(step_frac=p.step_frac, horizon_eps=p.horizon_eps, r_escape=p.r_escape,
                               xi_eps=p.xi_eps, euler_div=p.euler_div, max_steps=p.max_steps,
                               record_disk=p.record_disk, disk_rmin=p.disk_rmin,
-                              disk_rmax=p.disk_rmax)
+                              disk_rmax=p.disk_rmax, pole_mode=p.pole_mode)
 
 
 def pixel_ab(cam: W.Camera, ids):

@@ -79,7 +79,8 @@ CAM = W.Camera(0.5, 1000.0, 1.0, 8, 8, -5.0, 5.0, -5.0, 5.0)
 @pytest.mark.parametrize("field,value", [
     ("step_frac", 0.0), ("step_frac", math.inf), ("horizon_eps", 0.0), ("r_escape", -1.0),
     ("xi_eps", 0.0), ("euler_div", 0.5), ("max_steps", 0), ("call_steps", -1), ("precision", 5),
-    ("flags", 8), ("fp64_horizon", -1.0), ("fp64_pole", math.nan), ("fp64_turn", math.inf)])
+    ("flags", 8), ("fp64_horizon", -1.0), ("fp64_pole", math.nan), ("fp64_turn", math.inf),
+    ("pole_mode", 3), ("pole_mode", -1)])
 def test_invalid_params_rejected(lib, field, value):
     p = G.params_struct(W.Params())
     setattr(p, field, value)
@@ -122,6 +123,15 @@ def test_invalid_state_rejected(lib):
     arr[1].first = 0
     s = _state(128, 128)
     assert G.load().gray_camera_init(arr, 2, ctypes.byref(p), ctypes.byref(s), None) == G.GRAY_EINVAL
+
+
+def test_fp32c_supports_only_the_production_pole_treatment(lib):
+    p = G.params_struct(W.Params(precision="fp32c", pole_mode=G.GRAY_POLE_NONE))
+    s = _state(64, 64, lo=0x9000)
+    assert _call_init([CAM], p, s) == G.GRAY_EUNSUPPORTED
+    assert _call_integrate([CAM], p, s) == G.GRAY_EUNSUPPORTED
+    p64 = G.params_struct(W.Params(pole_mode=G.GRAY_POLE_EULER_CROSSING))
+    assert G.gray_workspace_size(64, 1, p64) > 0
 
 
 def test_workspace_checked(lib):
