@@ -96,6 +96,8 @@ typedef enum {
 #define GRAY_RECORD_DISK 1u /* record the first equatorial crossing (Sec. 3) */
 #define GRAY_WORKLIST 4u    /* work-list mode, see gray_state                */
 #define GRAY_WORKLIST_SLACK (1 << 20) /* extra list entries a call may leave unused */
+#define GRAY_MAX_PHOTONS 2147482623LL /* largest n (2^31 - 1025): photon ids, launch
+                                         order and queue positions are 32-bit */
 #define GRAY_SLOTS 2u       /* slot mode, for callers that keep many requests in
                                one resident photon pool (continuous batching):
                                `cams` is a slot table and camera k covers photon

@@ -62,7 +62,8 @@ static_assert(kMaxListWaves * kSpan <= GRAY_WORKLIST_SLACK, "list slack covers e
 constexpr size_t kWsHeader = 512;      // WsHeader, padded
 constexpr int kOrderBins = 32;         // scheduling-key buckets
 constexpr unsigned kOrderBlocks = 2048; // blocks of the ordering passes, at most
-constexpr int64_t kMaxPhotons = (int64_t)1 << 31;
+static_assert(GRAY_MAX_PHOTONS + (int64_t)(kQueueChunk * kMaxGrab + kSpan) < ((int64_t)1 << 31),
+              "ids, queue positions and their overshoot fit in 32 bits");
 
 // Start of the workspace: queue counter and the ordering pass's counts.
 struct WsHeader {
@@ -897,7 +898,7 @@ static int validate_cameras(const gray_camera *cams, int32_t ncam, int64_t n, ui
 static int validate_state(const gray_state *s, const gray_params *p)
 {
     if (!s) return GRAY_EINVAL;
-    if (s->n < 0 || s->n >= kMaxPhotons - (int64_t)(kQueueChunk * kMaxGrab + kSpan)) return GRAY_EINVAL;
+    if (s->n < 0 || s->n > GRAY_MAX_PHOTONS) return GRAY_EINVAL;
     if (s->n == 0) return GRAY_OK;
     if (s->stride < s->n || s->stride % kWave != 0) return GRAY_EINVAL;
     if (!s->x || !s->status || !s->steps || !s->cam) return GRAY_EINVAL;
@@ -1018,7 +1019,7 @@ using namespace gray;
 
 extern "C" size_t gray_workspace_size(int64_t n, int32_t ncam, const gray_params *p)
 {
-    if (n < 0 || n >= kMaxPhotons || ncam < 1 || validate_params(p) != GRAY_OK) return 0;
+    if (n < 0 || n > GRAY_MAX_PHOTONS || ncam < 1 || validate_params(p) != GRAY_OK) return 0;
     return ws_layout(n, ncam, p->flags).total;
 }
 

@@ -32,6 +32,8 @@ GRAY_WORKLIST_SLACK = 1 << 20
 PRECISIONS = {"fp64": GRAY_FP64, "fp32c": GRAY_FP32C}
 
 
+GRAY_MAX_PHOTONS = 2147482623
+
 # gray_params.pole_mode
 GRAY_POLE_MONITOR, GRAY_POLE_EULER_CROSSING, GRAY_POLE_NONE = 0, 1, 2
 

@@ -134,6 +134,18 @@ def test_fp32c_supports_only_the_production_pole_treatment(lib):
     assert G.gray_workspace_size(64, 1, p64) > 0
 
 
+def test_photon_count_limit(lib):
+    p = G.params_struct(W.Params())
+    n = G.GRAY_MAX_PHOTONS
+    assert G.gray_workspace_size(n, 1, p) > 0
+    assert G.gray_workspace_size(n + 1, 1, p) == 0
+    big = W.Camera(0.5, 1000.0, 1.0, 1, n + 1, -5, 5, -5, 5)
+    s = _state(n + 1, (n + 1 + 63) // 64 * 64)
+    assert _call_init([big], p, s) == G.GRAY_EINVAL
+    assert _call_integrate([big], p, s) == G.GRAY_EINVAL
+    assert _call_classify([big], p, s) == G.GRAY_EINVAL
+
+
 def test_workspace_checked(lib):
     p = G.params_struct(W.Params())
     s = _state(64, 64)

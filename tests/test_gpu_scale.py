@@ -1,5 +1,6 @@
 """Full-size workloads through the C ABI, checked against the oracle on
-deterministic samples of their rays (gathered on the device):
+deterministic samples of their rays (gathered on the device), and a batch
+of 2^27 photons for the large-index paths:
 
 * the 4096 x 4096 a = 0.9375, i = 17 deg grid with the equatorial recorder
   on, in FP32C (the precision this workload is specified in);
@@ -72,3 +73,25 @@ def test_c4_sweep_one_launch_fp64_sampled():
         bad += rep.flag_mismatch + rep.state_bad + rep.counter_bad
         assert rep.step_mismatch <= max(1, 0.002 * rep.n), (k, rep)
     assert bad == 0
+
+
+def test_large_batch_every_photon_advances_once_per_call():
+    """2^27 photons in one batch (134M: ids, launch-order entries and queue
+    positions span 1/16 of their 32-bit range, grabs are 512 ids): with
+    call_steps = 1 each call advances every running photon by exactly one
+    step."""
+    import torch
+    cam = W.Camera(0.6, 1000.0, W.deg(40.0), 8192, 16384, -12.0, 12.0, -12.0, 12.0)
+    assert cam.n == 1 << 27
+    b = G.Batch([cam], W.Params(call_steps=1), counters=False, mark=False)
+    b.camera_init()
+    for k in (1, 2):
+        b.integrate()
+        torch.cuda.synchronize()
+        steps = b.steps[: b.n]
+        assert int((steps == k).sum().item()) == b.n, k
+    assert int((b.status[: b.n] == G.RUNNING).sum().item()) == b.n
+    res = b.classify(xf=False, cons=False, counts=True)
+    assert res.counts.view(-1, 5).cpu().numpy()[0].tolist() == [b.n, 0, 0, 0, 0]
+    del b, res
+    torch.cuda.empty_cache()
