@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 # Algorithmic flops per accepted photon-step of the integrate kernel (common
 # path: RK4 + step size + null-condition check), weights add/mul 1, fma 2,
 # div/sqrt/sin/cos 1; produced by csrc/flopcount.cpp and checked by the tests.
-F_STEP = {"fp64": 644, "fp32c": 644}
+F_STEP = {"fp64": 572, "fp32c": 572}
 # MI355X published vector peaks, TFLOP/s (256 CUs at 2.4 GHz).
 PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 
@@ -271,7 +271,7 @@ def ring_study(np) -> dict:
     edge_on = [r for r in rings if r.incl_deg == 90]
     timing.update({
         "configs": len(rings),
-        "tflops": 644 * timing["photon_steps"] / (timing["integrate_ms"] * 1e-3) / 1e12,
+        "tflops": F_STEP["fp64"] * timing["photon_steps"] / (timing["integrate_ms"] * 1e-3) / 1e12,
         "unfinished_rays": int(sum(r.unfinished for r in rings)),
         "mean_radius_minus_fit": {"max_abs": float(np.abs(dR).max()), "rms": float(np.sqrt((dR ** 2).mean()))},
         "asymmetry_minus_fit": {"max_abs": float(np.abs(dA).max()), "rms": float(np.sqrt((dA ** 2).mean()))},

@@ -265,7 +265,13 @@ GRAY_HD Spin<T> make_spin(T a)
 // Geodesic acceleration given sin and cos of theta (see the file comment),
 // written out operation by operation: one reciprocal of Sigma Delta sin gives
 // 1/Sigma, 1/Delta and cot; every contraction is shaped into fused
-// multiply-adds.
+// multiply-adds. With rho^2 = r^2 + a^2 the identity rho^2 - a^2 sin^2 = Sigma
+// gives the short forms used below:
+//   X = (a k^t - rho^2 k^phi) / Sigma  = a P / Sigma - k^phi,
+//   P cot = cot k^t - a sin cos k^phi, with P = k^t - a sin^2 k^phi,
+//   a^2 k^t^2 - 2 a rho^2 k^t k^phi + a^2 sin^2 rho^2 k^phi^2
+//                                       = Sigma^2 X^2 - rho^2 Sigma k^phi^2.
+// At2 and Aph2 are half of the lowered components A_t and A_phi / sin^2.
 template <class T>
 GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr,
                    T &dkth, T &dkph)
@@ -283,41 +289,39 @@ GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T 
     const T isig = del * si3;
     const T idel = sig * si3;
     const T cot = c * (sd * i3);
-    const T q = r * isig;
-    const T w = fma(T(-2) * q, q, isig);
+    const T q = r * isig;                                    // r / Sigma
+    const T w = fma(T(-2) * q, q, isig);                     // (Sigma - 2 r^2) / Sigma^2
     const T W = rho2 * isig;
-    const T F = fma(B.a2_2 * s2, q, rho2);
-    const T hdrgrr = idel * fma(-(sig * idel), r - T(1), r);   // (1/2) d_r g_rr
+    const T F = fma(B.a2_2 * s2, q, rho2);                   // g_phiphi / sin^2
+    const T hdrgrr = idel * fma(-(sig * idel), r - T(1), r); // (1/2) d_r g_rr
     const T P = fma(-(a * s2), kph, kt);
     const T kr2 = kr * kr, kth2 = kth * kth, kph2 = kph * kph;
+    const T aq2 = B.a_2 * q;                                 // 2 a r / Sigma
+    const T X = fma(a * isig, P, -kph);
+    const T r_2 = r + r;
 
-    // A_t
-    const T X = fma(a * isig, kt, -(W * kph));
-    const T At = fma((w + w) * kr, P, ((B.a_4 * (q * sc)) * kth) * X);
-    // A_phi / sin^2
+    // A_t / 2
+    const T At2 = fma(w * kr, P, ((aq2 * sc) * kth) * X);
+    // A_phi / (2 sin^2)
     const T t1 = fma(-(a * w), P, r * kph);
-    const T u = fma(-(a * sc), kph, cot * kt);
-    const T Fc = F * cot;
-    const T inner = fma(-(B.a_4 * (q * W)), u, (Fc + Fc) * kph);
-    const T Aph = fma(kth, inner, (kr + kr) * t1);
+    const T Aph2 = fma(kth * cot, fma(-(aq2 * W), P, F * kph), kr * t1);
     // A_r
     T Ar = hdrgrr * kr2;
     Ar = fma(-((B.a2_2 * sc) * idel * kr), kth, Ar);
     Ar = fma(-r, fma(s2, kph2, kth2), Ar);
     Ar = fma(-(w * P), P, Ar);
-    // A_theta
-    T e = (a2 * isig) * (kt * kt);
-    e = fma(-((B.a_2 * W) * kt), kph, e);
-    e = fma((a2 * s2) * W, kph2, e);
+    // A_theta = sin cos g + 2 r k^r k^theta
+    const T G = fma(-(q + q), rho2, F);
     T g = a2 * fma(idel, kr2, -kth2);
-    g = fma(-F, kph2, g);
-    g = fma(-(q + q), e, g);
-    const T Ath = fma(sc, g, ((r + r) * kr) * kth);
+    g = fma(-G, kph2, g);
+    g = fma(-(r_2 * X), X, g);
+    const T Ath = fma(sc, g, (r_2 * kr) * kth);
 
-    dkt = fma((B.a_2 * q) * s2, Aph, F * At) * idel;
+    const T idel2 = idel + idel;
+    dkt = fma(aq2 * s2, Aph2, F * At2) * idel2;
     dkr = -Ar * (del * isig);
     dkth = -Ath * isig;
-    dkph = fma((q + q) - T(1), Aph, (B.a_2 * q) * At) * idel;
+    dkph = fma(fma(T(2), q, T(-1)), Aph2, aq2 * At2) * idel2;
 }
 
 // f(y) of the geodesic equation given sin and cos of y.th.
