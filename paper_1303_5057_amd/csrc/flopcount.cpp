@@ -55,7 +55,7 @@ int main()
     // static limit.
     StepConst<Flop> K;
     K.B = make_spin(Flop(0.9)); K.rbh = horizon_radius(0.9);
-    K.step_frac = 1.0 / 32; K.xi_eps = 1e-3; K.euler_div = 9.0;
+    K.step_frac = 1.0 / 32; K.xi_eps = 1e-3; K.euler_inv = 1.0 / 9.0;
     State<double> x0;
     camera_state(0.9, 12.0, 1.0, 4.0, 3.0, x0);
     State<Flop> x;

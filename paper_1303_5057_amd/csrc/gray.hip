@@ -375,7 +375,7 @@ struct IntArgs {
     unsigned *cam_done;         // per-camera count of photons that stopped
     unsigned long long *wave_iters; // += loop iterations with a busy lane
     int64_t n, stride;
-    double step_frac, xi_eps, euler_div, r_escape;
+    double step_frac, xi_eps, euler_inv, r_escape;
     double fp64_horizon, fp64_pole, fp64_turn;
     int32_t max_steps, call_steps;
     uint32_t flags;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     Lane<P> L;
     StepConst<double> K;
     StepConst<float> Kf;
-    double rcap = 0.0, rmark = 0.0, dmin = 0.0, dmax = 0.0;
+    double rcap = 0.0;
     float r64 = 0.0f;
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
@@ -487,14 +487,14 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     unsigned chunk_next = 0, chunk_end = 0;
     bool exhausted = false;
     // Two-ended queue (dense mode, where the launch order puts the photons
-    // expected to take longest first): of the two waves that share a SIMD,
-    // the one in the lower hardware slot (HW_ID bits 3:0) issues first when
-    // both are ready, and advances at close to the rate of a wave alone,
-    // while the other gets what is left (measured: about 2.4 vs 5 us per
-    // step on the same work). Even slots therefore take ids from the head of
-    // the queue and odd slots from its tail, so the longest photons run in
-    // the favoured slot.
-    const bool from_tail = A.two_ended && (__builtin_amdgcn_s_getreg(4 | (3 << 11)) & 1u) != 0u;
+    // expected to take longest first): of the waves that share a SIMD, the
+    // one in hardware slot 0 (HW_ID bits 3:0) issues first when several are
+    // ready, and advances at close to the rate of a wave alone, while the
+    // others get what is left (measured with two waves: about 2.4 vs 5 us
+    // per step on the same work). Slot 0 therefore takes ids from the head
+    // of the queue and the other slots from its tail, so the longest
+    // photons run in the favoured slot.
+    const bool from_tail = A.two_ended && (__builtin_amdgcn_s_getreg(4 | (3 << 11)) & 15u) != 0u;
     // Queue length: the length of the work list or of the launch order.
     const int64_t nq = (int64_t)__builtin_amdgcn_readfirstlane(*A.work_in_count);
     // A grab takes `grab` ids (a multiple of 64): large enough to keep the
@@ -550,19 +550,16 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                         K.rbh = cm.rbh;
                         K.step_frac = A.step_frac;
                         K.xi_eps = A.xi_eps;
-                        K.euler_div = A.euler_div;
+                        K.euler_inv = A.euler_inv;
                         if constexpr (P == GRAY_FP32C) {
                             Kf.B = make_spin((float)cm.a);
                             Kf.rbh = (float)cm.rbh;
                             Kf.step_frac = (float)A.step_frac;
                             Kf.xi_eps = (float)(0.5 * A.xi_eps);
-                            Kf.euler_div = (float)A.euler_div;
+                            Kf.euler_inv = (float)A.euler_inv;
                             r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
                         }
                         rcap = cm.rcap;
-                        rmark = cm.rmark;
-                        dmin = cm.disk_rmin;
-                        dmax = cm.disk_rmax;
                         nsteps = A.steps[id];
                         ncall = 0;
                         ne = A.counters ? A.counters[0 * S + id] : 0;
@@ -587,42 +584,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
         bool stop_now = false, keep = false;
         iters += ballot(active) != 0ull;
         if (active) {
-            const State<double> xp = L.value();
-            State<double> x;
-            int fl;
-            if constexpr (P == GRAY_FP64) {
-                fl = rk4_step<PM>(K, L.x, L.s, L.c);
-                x = L.x;
-            } else {
-                auto &F = L;
-                const bool need64 = F.hi.r < r64 || F.s < (float)A.fp64_pole ||
-                                    fabsf(F.hi.kr) < (float)A.fp64_turn * fabsf(F.hi.kt);
-                fl = -2;
-                if (!need64) fl = rk4_step_c32(Kf, F.hi, F.lo, F.s, F.c, Kf.xi_eps);
-                if (fl == -2) {
-                    x = xp;
-                    double s64, c64;
-                    sin_cos(x.th, s64, c64);
-                    fl = rk4_step(K, x, s64, c64);
-                    if (fl >= 0) {
-                        F.set(x);
-                        ++n64;
-                    }
-                }
-                x = F.value();
-            }
-            int32_t st = GRAY_RUNNING;
-            if (fl < 0) {
-                st = GRAY_NONFINITE;
-            } else {
-                ++nsteps;
-                ++ncall;
-                ne += fl & 1;
-                nr += (fl >> 1) & 1;
+            // Equatorial-crossing recorder and 2 r_bh mark of one accepted
+            // step from xp to x.
+            auto record = [&](const State<double> &xp, const State<double> &x) {
                 if (record_disk && !hit && (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0) {
                     const double f = (kHalfPi - xp.th) / (x.th - xp.th);
                     const double rc = xp.r + f * (x.r - xp.r);
-                    if (rc >= dmin && rc <= dmax) {
+                    // recorder window of the photon's camera, read when needed
+                    const DevCam &cw = A.cams[A.cam[id]];
+                    if (rc >= cw.disk_rmin && rc <= cw.disk_rmax) {
                         double E, Lz, Q;
                         conserved(K.B.a, x, E, Lz, Q);
                         A.disk[0 * S + id] = rc;
@@ -631,6 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                         hit = true;
                     }
                 }
+                const double rmark = K.rbh + K.rbh;
                 if (A.mark && xp.r >= rmark && x.r < rmark) {
                     A.mark[0 * S + id] = xp.t;
                     A.mark[1 * S + id] = xp.r;
@@ -641,6 +612,42 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                     A.mark[6 * S + id] = xp.kth;
                     A.mark[7 * S + id] = xp.kph;
                 }
+            };
+            State<double> x;
+            int fl;
+            if constexpr (P == GRAY_FP64) {
+                fl = rk4_step<PM>(K, L.x, L.s, L.c, record);
+                x = L.x;
+            } else {
+                const State<double> xp = L.value();
+                auto &F = L;
+                const bool need64 = F.hi.r < r64 || F.s < (float)A.fp64_pole ||
+                                    fabsf(F.hi.kr) < (float)A.fp64_turn * fabsf(F.hi.kt);
+                fl = -2;
+                if (!need64) fl = rk4_step_c32(Kf, F.hi, F.lo, F.s, F.c, Kf.xi_eps);
+                if (fl == -2) {
+                    // FP64 step of the FP32C kernel: sin/cos coefficients in
+                    // vector registers (its scalar registers are the scarce ones)
+                    x = xp;
+                    double s64, c64;
+                    sin_cos<false>(x.th, s64, c64);
+                    fl = rk4_step<kPoleMonitor, false>(K, x, s64, c64);
+                    if (fl >= 0) {
+                        F.set(x);
+                        ++n64;
+                    }
+                }
+                x = F.value();
+                if (fl >= 0) record(xp, x);
+            }
+            int32_t st = GRAY_RUNNING;
+            if (fl < 0) {
+                st = GRAY_NONFINITE;
+            } else {
+                ++nsteps;
+                ++ncall;
+                ne += fl & 1;
+                nr += (fl >> 1) & 1;
                 if (!finite_state(x)) st = GRAY_NONFINITE;
                 else if (x.r < rcap) st = GRAY_CAPTURED;
                 else if (x.r > A.r_escape && x.kr > 0.0) st = GRAY_ESCAPED;
@@ -1171,7 +1178,7 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.stride = s->stride;
     A.step_frac = p->step_frac;
     A.xi_eps = p->xi_eps;
-    A.euler_div = p->euler_div;
+    A.euler_inv = 1.0 / p->euler_div;
     A.r_escape = p->r_escape;
     A.fp64_horizon = p->fp64_horizon;
     A.fp64_pole = p->fp64_pole;

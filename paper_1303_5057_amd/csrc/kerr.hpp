@@ -26,6 +26,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace gray {
 
@@ -77,19 +78,49 @@ GRAY_HD double quot(double a, double b) { return a * rcp(b); }
 // Two Horner chains in z evaluated side by side:
 //   ps = (..((s[0] z + s[1]) z + s[2]) z ..) + s[NS-1]
 //   pc = (..((c[0] z + c[1]) z + c[2]) z ..) + c[NC-1]
-// On the device each step is one VOP3 v_fma_f64 whose addend is a register
-// it does not overwrite. (Written as fma(), the compiler selects the
-// two-address v_fmac_f64, whose accumulator is the addend, and so copies
-// every loop-invariant coefficient into it first: one extra move per step.)
-// One asm statement holds both chains, interleaved, so no wait states are
-// inserted between them; the steps are dependent plain FP64 FMAs.
+// On the device each step is one VOP3 v_fma_f64 whose addend, a coefficient
+// held in a scalar register pair, it does not overwrite (the leading
+// coefficient sits in vector registers: an instruction reads at most one
+// scalar source). (Written as fma(),
+// the compiler selects the two-address v_fmac_f64, whose accumulator is the
+// addend, and so copies every loop-invariant coefficient into it first: one
+// extra move per step; and coefficients kept in vector registers cost 34 of
+// them per lane for the whole loop.) One asm statement holds both chains,
+// interleaved, so no wait states are inserted between them; the steps are
+// dependent plain FP64 FMAs.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define GRAY_HORNER_STEP(acc, k) "v_fma_f64 %" #acc ", %2, %" #acc ", %" #k "\n\t"
+#endif
+
+// The coefficients are asm operands of constraint K: "s" keeps them in
+// scalar registers (the FP64 integrator, where 34 vector registers per lane
+// decide how many waves fit on a SIMD), "v" in vector registers (kernels
+// whose scalar registers are the scarcer resource).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GRAY_SINCOS_SMALL_ASM(K)                                                         \
+    asm("v_fma_f64 %0, %2, %3, %4\n\t"                                                  \
+        "v_fma_f64 %1, %2, %7, %8\n\t"                                                  \
+        GRAY_HORNER_STEP(0, 5) GRAY_HORNER_STEP(1, 9) GRAY_HORNER_STEP(0, 6)             \
+        GRAY_HORNER_STEP(1, 10)                                                          \
+        : "=&v"(ps), "=&v"(pc)                                                           \
+        : "v"(z), "v"(S0), K(S1), K(S2), K(S3), "v"(C0), K(C1), K(C2), K(C3))
+#define GRAY_SINCOS_FULL_ASM(K)                                                          \
+    asm("v_fma_f64 %0, %2, %3, %4\n\t"                                                  \
+        "v_fma_f64 %1, %2, %11, %12\n\t"                                                \
+        GRAY_HORNER_STEP(0, 5) GRAY_HORNER_STEP(1, 13) GRAY_HORNER_STEP(0, 6)            \
+        GRAY_HORNER_STEP(1, 14) GRAY_HORNER_STEP(0, 7) GRAY_HORNER_STEP(1, 15)           \
+        GRAY_HORNER_STEP(0, 8) GRAY_HORNER_STEP(1, 16) GRAY_HORNER_STEP(0, 9)            \
+        GRAY_HORNER_STEP(1, 17) GRAY_HORNER_STEP(0, 10) GRAY_HORNER_STEP(1, 18)          \
+        GRAY_HORNER_STEP(1, 19)                                                          \
+        : "=&v"(ps), "=&v"(pc)                                                           \
+        : "v"(z), "v"(S0), K(S1), K(S2), K(S3), K(S4), K(S5), K(S6), K(S7), "v"(C0),     \
+          K(C1), K(C2), K(C3), K(C4), K(C5), K(C6), K(C7), K(C8))
 #endif
 
 // sin and cos of a small angle, |d| <= 1/16, from their Taylor series (sin
 // to d^9, cos to d^8: truncation below 3e-19). The stage offsets of a step
 // obey |d| <= Delta of eq. (2) to first order, so this covers them.
+template <bool SGPR = true>
 GRAY_HD void sincos_small(double d, double &sd, double &cd)
 {
     const double z = d * d;
@@ -99,14 +130,8 @@ GRAY_HD void sincos_small(double d, double &sd, double &cd)
                      C2 = 4.1666666666666664e-02, C3 = -0.5;
     double ps, pc;
 #if defined(__HIP_DEVICE_COMPILE__)
-    asm("v_fma_f64 %0, %2, %3, %4\n\t"
-        "v_fma_f64 %1, %2, %7, %8\n\t"
-        GRAY_HORNER_STEP(0, 5)
-        GRAY_HORNER_STEP(1, 9)
-        GRAY_HORNER_STEP(0, 6)
-        GRAY_HORNER_STEP(1, 10)
-        : "=&v"(ps), "=&v"(pc)
-        : "v"(z), "v"(S0), "v"(S1), "v"(S2), "v"(S3), "v"(C0), "v"(C1), "v"(C2), "v"(C3));
+    if constexpr (SGPR) GRAY_SINCOS_SMALL_ASM("s");
+    else GRAY_SINCOS_SMALL_ASM("v");
 #else
     ps = fma(z, fma(z, fma(z, S0, S1), S2), S3);
     pc = fma(z, fma(z, fma(z, C0, C1), C2), C3);
@@ -119,6 +144,7 @@ GRAY_HD void sincos_small(double d, double &sd, double &cd)
 // pi/2 with a two-term split of pi/2 (FMA keeps the first subtraction exact),
 // then Taylor series on |r| <= pi/4 (sin to r^17, cos to r^18, truncation
 // below 1e-19), then the quadrant.
+template <bool SGPR = true>
 GRAY_HD void sincos_full(double x, double &s, double &c)
 {
     const double k = rint(x * 0.6366197723675814);
@@ -135,24 +161,8 @@ GRAY_HD void sincos_full(double x, double &s, double &c)
                      C6 = -1.388888888888889e-03, C7 = 4.1666666666666664e-02, C8 = -0.5;
     double ps, pc;
 #if defined(__HIP_DEVICE_COMPILE__)
-    asm("v_fma_f64 %0, %2, %3, %4\n\t"
-        "v_fma_f64 %1, %2, %11, %12\n\t"
-        GRAY_HORNER_STEP(0, 5)
-        GRAY_HORNER_STEP(1, 13)
-        GRAY_HORNER_STEP(0, 6)
-        GRAY_HORNER_STEP(1, 14)
-        GRAY_HORNER_STEP(0, 7)
-        GRAY_HORNER_STEP(1, 15)
-        GRAY_HORNER_STEP(0, 8)
-        GRAY_HORNER_STEP(1, 16)
-        GRAY_HORNER_STEP(0, 9)
-        GRAY_HORNER_STEP(1, 17)
-        GRAY_HORNER_STEP(0, 10)
-        GRAY_HORNER_STEP(1, 18)
-        GRAY_HORNER_STEP(1, 19)
-        : "=&v"(ps), "=&v"(pc)
-        : "v"(z), "v"(S0), "v"(S1), "v"(S2), "v"(S3), "v"(S4), "v"(S5), "v"(S6), "v"(S7),
-          "v"(C0), "v"(C1), "v"(C2), "v"(C3), "v"(C4), "v"(C5), "v"(C6), "v"(C7), "v"(C8));
+    if constexpr (SGPR) GRAY_SINCOS_FULL_ASM("s");
+    else GRAY_SINCOS_FULL_ASM("v");
 #else
     ps = S0;
     for (double sk : {S1, S2, S3, S4, S5, S6, S7}) ps = fma(z, ps, sk);
@@ -168,19 +178,21 @@ GRAY_HD void sincos_full(double x, double &s, double &c)
     c = ((q + 1) & 2) ? -b : b;
 }
 
-GRAY_HD void sin_cos(double x, double &s, double &c) { sincos_full(x, s, c); }
+template <bool SGPR = true>
+GRAY_HD void sin_cos(double x, double &s, double &c) { sincos_full<SGPR>(x, s, c); }
 
 // sin and cos of th = th0 + d from those of th0 (angle addition with the
 // small-angle series); falls back to the full evaluation when |d| > 1/16.
+template <bool SGPR = true>
 GRAY_HD void shift_sincos(double s0, double c0, double d, double th, double &s, double &c)
 {
     if (fabs(d) <= 0.0625) {
         double sd, cd;
-        sincos_small(d, sd, cd);
+        sincos_small<SGPR>(d, sd, cd);
         s = fma(s0, cd, c0 * sd);
         c = fma(c0, cd, -(s0 * sd));
     } else {
-        sincos_full(th, s, c);
+        sincos_full<SGPR>(th, s, c);
     }
 }
 
@@ -247,7 +259,7 @@ GRAY_HD void shift_sincos(float s0, float c0, float d, float th, float &s, float
 // Spin-dependent constants of one photon's spacetime.
 template <class T>
 struct Spin {
-    T a, a2, a_2, a_4, a2_2;   // a, a^2, 2a, 4a, 2a^2
+    T a, a2;   // a, a^2
 };
 
 template <class T>
@@ -256,9 +268,6 @@ GRAY_HD Spin<T> make_spin(T a)
     Spin<T> B;
     B.a = a;
     B.a2 = a * a;
-    B.a_2 = T(2) * a;
-    B.a_4 = T(4) * a;
-    B.a2_2 = T(2) * B.a2;
     return B;
 }
 
@@ -290,13 +299,15 @@ GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T 
     const T idel = sig * si3;
     const T cot = c * (sd * i3);
     const T q = r * isig;                                    // r / Sigma
-    const T w = fma(T(-2) * q, q, isig);                     // (Sigma - 2 r^2) / Sigma^2
+    const T q2 = q + q;
+    const T w = fma(-q2, q, isig);                           // (Sigma - 2 r^2) / Sigma^2
     const T W = rho2 * isig;
-    const T F = fma(B.a2_2 * s2, q, rho2);                   // g_phiphi / sin^2
+    const T F = fma(a2 * s2, q2, rho2);                      // g_phiphi / sin^2
     const T hdrgrr = idel * fma(-(sig * idel), r - T(1), r); // (1/2) d_r g_rr
     const T P = fma(-(a * s2), kph, kt);
     const T kr2 = kr * kr, kth2 = kth * kth, kph2 = kph * kph;
-    const T aq2 = B.a_2 * q;                                 // 2 a r / Sigma
+    const T aq2 = a * q2;                                    // 2 a r / Sigma
+    const T idel2 = idel + idel;
     const T X = fma(a * isig, P, -kph);
     const T r_2 = r + r;
 
@@ -307,17 +318,16 @@ GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T 
     const T Aph2 = fma(kth * cot, fma(-(aq2 * W), P, F * kph), kr * t1);
     // A_r
     T Ar = hdrgrr * kr2;
-    Ar = fma(-((B.a2_2 * sc) * idel * kr), kth, Ar);
+    Ar = fma(-((a2 * sc) * idel2 * kr), kth, Ar);
     Ar = fma(-r, fma(s2, kph2, kth2), Ar);
     Ar = fma(-(w * P), P, Ar);
     // A_theta = sin cos g + 2 r k^r k^theta
-    const T G = fma(-(q + q), rho2, F);
+    const T G = fma(-q2, rho2, F);
     T g = a2 * fma(idel, kr2, -kth2);
     g = fma(-G, kph2, g);
     g = fma(-(r_2 * X), X, g);
     const T Ath = fma(sc, g, (r_2 * kr) * kth);
 
-    const T idel2 = idel + idel;
     dkt = fma(aq2 * s2, Aph2, F * At2) * idel2;
     dkr = -Ar * (del * isig);
     dkth = -Ath * isig;
@@ -391,21 +401,46 @@ constexpr int kPoleMonitor = 0, kPoleEulerCrossing = 1, kPoleNone = 2;
 template <class T>
 struct StepConst {
     Spin<T> B;
-    T rbh, step_frac, xi_eps, euler_div;
+    T rbh, step_frac, xi_eps;
+    T euler_inv;   // 1 / (the Euler fallback's step divisor, 9 in Sec. 2)
 };
 
 // One accepted step of the production scheme (Sec. 2): classical RK4 with h
 // from eq. (2); if the proposal violates the null condition, |xi + 1| > eps
 // (eq. 4), one forward-Euler step of h / euler_div from the same start
-// replaces it; then the remap of eq. (3). PM selects the paper's earlier
+// replaces it; then the remap of eq. (3). observe(start, end) sees every
+// accepted step just before the state is overwritten (so a caller that needs
+// the start state keeps no copy of it). PM selects the paper's earlier
 // treatments instead: kPoleEulerCrossing replaces a step that ends across a
 // pole by one forward-Euler step of the same h; kPoleNone keeps every RK4
 // step. (s, c) = sin/cos(x.th) on entry and
 // on exit (always recomputed from the final theta, so a step is a function of
 // the stored state alone). Returns bit 0 = Euler fallback, bit 1 = remap, or
 // -1 when h is not a positive finite number (state kept).
-template <int PM = kPoleMonitor, class T>
-GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
+// sin/cos helpers of the step template: the FP64 versions take the
+// coefficient placement SC, other number types use their own overloads.
+template <bool SC, class T>
+GRAY_HD void step_shift_sincos(T s0, T c0, T d, T th, T &s, T &c)
+{
+    if constexpr (std::is_same<T, double>::value) shift_sincos<SC>(s0, c0, d, th, s, c);
+    else shift_sincos(s0, c0, d, th, s, c);
+}
+
+template <bool SC, class T>
+GRAY_HD void step_sin_cos(T x, T &s, T &c)
+{
+    if constexpr (std::is_same<T, double>::value) sin_cos<SC>(x, s, c);
+    else sin_cos(x, s, c);
+}
+
+// Step observer that does nothing (see rk4_step).
+struct NoObserver {
+    template <class S>
+    GRAY_HD void operator()(const S &, const S &) const {}
+};
+
+template <int PM = kPoleMonitor, bool SC = true, class T, class Obs = NoObserver>
+GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&observe = Obs())
 {
     // eq. (2): h1 = Delta r / D1 with D1 = |k^r| + r (|k^th| + |k^ph|), and
     // h2 = (r - r_bh) / (2 |k^r|); h2 < h1 is decided without dividing.
@@ -419,32 +454,37 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
     if (!(h > T(0) && h < T(INFINITY))) return -1;
     const T hh = T(0.5) * h;
 
-    State<T> k1, k2, k3, k4, y;
+    // The stage derivatives are summed as they come, k1 + 2 k2 + 2 k3 + k4
+    // from left to right, so k2 and k3 need no registers once used; k1 stays
+    // for the Euler fallback.
+    State<T> k1, k, y, acc;
     T sy, cy;
     deriv(K.B, x, s, c, k1);
     y = axpy(x, hh, k1);
-    shift_sincos(s, c, y.th - x.th, y.th, sy, cy);
-    deriv(K.B, y, sy, cy, k2);
-    y = axpy(x, hh, k2);
-    shift_sincos(s, c, y.th - x.th, y.th, sy, cy);
-    deriv(K.B, y, sy, cy, k3);
-    y = axpy(x, h, k3);
-    shift_sincos(s, c, y.th - x.th, y.th, sy, cy);
-    deriv(K.B, y, sy, cy, k4);
+    step_shift_sincos<SC>(s, c, y.th - x.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k);
+    acc = axpy(k1, T(2), k);
+    y = axpy(x, hh, k);
+    step_shift_sincos<SC>(s, c, y.th - x.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k);
+    acc = axpy(acc, T(2), k);
+    y = axpy(x, h, k);
+    step_shift_sincos<SC>(s, c, y.th - x.th, y.th, sy, cy);
+    deriv(K.B, y, sy, cy, k);
 
     const T h6 = h * T(1.0 / 6.0);
     State<T> xn;
-#define GRAY_RK4(cmp) xn.cmp = fma(h6, k1.cmp + T(2) * (k2.cmp + k3.cmp) + k4.cmp, x.cmp)
+#define GRAY_RK4(cmp) xn.cmp = fma(h6, acc.cmp + k.cmp, x.cmp)
     GRAY_RK4(t); GRAY_RK4(r); GRAY_RK4(th); GRAY_RK4(ph);
     GRAY_RK4(kt); GRAY_RK4(kr); GRAY_RK4(kth); GRAY_RK4(kph);
 #undef GRAY_RK4
 
     int flags = 0;
-    sin_cos(xn.th, sy, cy);
+    step_sin_cos<SC>(xn.th, sy, cy);
     if constexpr (PM == kPoleMonitor) {
         const Metric<T> g = metric(K.B.a, K.B.a2, xn.r, sy, cy);
         if (xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps)) {
-            xn = axpy(x, quot(h, K.euler_div), k1);
+            xn = axpy(x, h * K.euler_inv, k1);
             flags |= 1;
         }
     } else if constexpr (PM == kPoleEulerCrossing) {
@@ -464,7 +504,8 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c)
         xn.kth = -xn.kth;
         flags |= 2;
     }
-    if (flags) sin_cos(xn.th, sy, cy);
+    if (flags) step_sin_cos<SC>(xn.th, sy, cy);
+    observe(x, xn);
     x = xn;
     s = sy;
     c = cy;
