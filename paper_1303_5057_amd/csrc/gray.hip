@@ -383,6 +383,99 @@ struct IntArgs {
     int32_t two_ended;          // odd wave slots take ids from the end of the queue
 };
 
+// Argument block fields of the running k_integrate, read again where they
+// are used. The persistent loop needs most of its pointers only when a
+// photon starts or stops; held in scalar registers across the loop, they and
+// the per-component addresses the compiler derives from them would crowd
+// out the stepping code's own scalar values (its sin/cos coefficients) and
+// spill. A scalar load from the kernel-argument segment inside an asm
+// statement can be neither hoisted nor combined. Valid only in kernels
+// whose sole argument is an IntArgs.
+template <class T, size_t OFF>
+__device__ __forceinline__ T int_arg()
+{
+    static_assert(sizeof(T) == 8, "64-bit fields only");
+    const auto kp = __builtin_amdgcn_kernarg_segment_ptr();
+    T v;
+    asm volatile("s_load_dwordx2 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(kp), "i"(OFF));
+    return v;
+}
+#define GRAY_ARG(f) int_arg<decltype(IntArgs::f), offsetof(IntArgs, f)>()
+
+// The pointer fields of IntArgs (its first 128 bytes), read back with one
+// or two scalar loads and a single wait: the eight per-photon arrays, and
+// the camera table and queue pointers.
+struct ArgPointers {
+    void *x, *lo;
+    int32_t *status, *steps;
+    const int32_t *cam;
+    int32_t *counters;
+    double *mark, *disk;
+    const DevCam *cams;
+    unsigned long long *queue;
+    const int32_t *work_in;
+    int32_t *work_out;
+    const unsigned *work_in_count;
+    unsigned *work_out_count;
+    unsigned *cam_done;
+    unsigned long long *wave_iters;
+};
+static_assert(sizeof(ArgPointers) == 128 && offsetof(IntArgs, x) == 0 && offsetof(IntArgs, lo) == 8 &&
+                  offsetof(IntArgs, status) == 16 && offsetof(IntArgs, steps) == 24 &&
+                  offsetof(IntArgs, cam) == 32 && offsetof(IntArgs, counters) == 40 &&
+                  offsetof(IntArgs, mark) == 48 && offsetof(IntArgs, disk) == 56 &&
+                  offsetof(IntArgs, cams) == 64 && offsetof(IntArgs, queue) == 72 &&
+                  offsetof(IntArgs, work_in) == 80 && offsetof(IntArgs, work_out) == 88 &&
+                  offsetof(IntArgs, work_in_count) == 96 && offsetof(IntArgs, work_out_count) == 104 &&
+                  offsetof(IntArgs, cam_done) == 112 && offsetof(IntArgs, wave_iters) == 120,
+              "ArgPointers mirrors the first 128 bytes of IntArgs");
+
+// N = 1: the per-photon arrays only (the rest left null); N = 2: all.
+template <int N>
+__device__ __forceinline__ ArgPointers arg_pointers()
+{
+    typedef unsigned u32x16 __attribute__((ext_vector_type(16)));
+    const auto kp = __builtin_amdgcn_kernarg_segment_ptr();
+    u32x16 v0, v1 = {};
+    if constexpr (N == 1)
+        asm volatile("s_load_dwordx16 %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v0) : "s"(kp));
+    else
+        asm volatile("s_load_dwordx16 %0, %2, 0\n\ts_load_dwordx16 %1, %2, 64\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&s"(v0), "=&s"(v1)
+                     : "s"(kp));
+    ArgPointers P;
+    uint64_t *w = (uint64_t *)&P;
+    for (int k = 0; k < 8; ++k) w[k] = (uint64_t)v0[2 * k] | ((uint64_t)v0[2 * k + 1] << 32);
+    for (int k = 0; k < 8; ++k) w[8 + k] = (uint64_t)v1[2 * k] | ((uint64_t)v1[2 * k + 1] << 32);
+    return P;
+}
+
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T *;
+
+// The same pointer as a global-memory one (accesses through a pointer read
+// back by int_arg would otherwise be generic, flat ones).
+template <class T>
+__device__ __forceinline__ global_ptr<T> glob(T *p) { return (global_ptr<T>)p; }
+
+// Element id of a component-major array of stride S, visited one component
+// after the other. The address advances in vector registers through an
+// empty asm statement, so the compiler cannot replace the walk by one
+// scalar base address per component.
+template <class T>
+struct Column {
+    global_ptr<T> p;
+    int64_t S;
+    __device__ __forceinline__ Column(T *base, int64_t stride, int64_t id) : p((global_ptr<T>)base + id), S(stride) {}
+    __device__ __forceinline__ T get() const { return *p; }
+    __device__ __forceinline__ void put(T v) const { *p = v; }
+    __device__ __forceinline__ void next()
+    {
+        p += S;
+        asm volatile("" : "+v"(p));
+    }
+};
+
 // Per-lane photon of the persistent loop. In FP64 the state is x; in FP32C
 // it is hi + lo (floats) and x is not kept between steps.
 template <int P>
@@ -392,20 +485,26 @@ template <>
 struct Lane<GRAY_FP64> {
     State<double> x;
     double s, c;
-    __device__ __forceinline__ void load(const IntArgs &A, int64_t id)
+    __device__ __forceinline__ void load(const void *xp, const void *, int64_t S, int64_t id)
     {
-        const double *X = (const double *)A.x;
-        const int64_t S = A.stride;
-        x.t = X[0 * S + id]; x.r = X[1 * S + id]; x.th = X[2 * S + id]; x.ph = X[3 * S + id];
-        x.kt = X[4 * S + id]; x.kr = X[5 * S + id]; x.kth = X[6 * S + id]; x.kph = X[7 * S + id];
+        Column<const double> X((const double *)xp, S, id);
+        double v[8];
+        for (int k = 0; k < 8; ++k) {
+            v[k] = X.get();
+            if (k < 7) X.next();
+        }
+        x.t = v[0]; x.r = v[1]; x.th = v[2]; x.ph = v[3];
+        x.kt = v[4]; x.kr = v[5]; x.kth = v[6]; x.kph = v[7];
         sin_cos(x.th, s, c);
     }
-    __device__ __forceinline__ void store(const IntArgs &A, int64_t id) const
+    __device__ __forceinline__ void store(void *xp, void *, int64_t S, int64_t id) const
     {
-        double *X = (double *)A.x;
-        const int64_t S = A.stride;
-        X[0 * S + id] = x.t; X[1 * S + id] = x.r; X[2 * S + id] = x.th; X[3 * S + id] = x.ph;
-        X[4 * S + id] = x.kt; X[5 * S + id] = x.kr; X[6 * S + id] = x.kth; X[7 * S + id] = x.kph;
+        const double v[8] = {x.t, x.r, x.th, x.ph, x.kt, x.kr, x.kth, x.kph};
+        Column<double> X((double *)xp, S, id);
+        for (int k = 0; k < 8; ++k) {
+            X.put(v[k]);
+            if (k < 7) X.next();
+        }
     }
     __device__ __forceinline__ State<double> value() const { return x; }
 };
@@ -414,24 +513,35 @@ template <>
 struct Lane<GRAY_FP32C> {
     State<float> hi, lo;
     float s, c;
-    __device__ __forceinline__ void load(const IntArgs &A, int64_t id)
+    __device__ __forceinline__ void load(const void *hp, const void *lp, int64_t S, int64_t id)
     {
-        const float *H = (const float *)A.x, *L = (const float *)A.lo;
-        const int64_t S = A.stride;
-        hi.t = H[0 * S + id]; hi.r = H[1 * S + id]; hi.th = H[2 * S + id]; hi.ph = H[3 * S + id];
-        hi.kt = H[4 * S + id]; hi.kr = H[5 * S + id]; hi.kth = H[6 * S + id]; hi.kph = H[7 * S + id];
-        lo.t = L[0 * S + id]; lo.r = L[1 * S + id]; lo.th = L[2 * S + id]; lo.ph = L[3 * S + id];
-        lo.kt = L[4 * S + id]; lo.kr = L[5 * S + id]; lo.kth = L[6 * S + id]; lo.kph = L[7 * S + id];
+        Column<const float> H((const float *)hp, S, id), L((const float *)lp, S, id);
+        float h[8], l[8];
+        for (int k = 0; k < 8; ++k) {
+            h[k] = H.get();
+            l[k] = L.get();
+            if (k < 7) {
+                H.next();
+                L.next();
+            }
+        }
+        hi.t = h[0]; hi.r = h[1]; hi.th = h[2]; hi.ph = h[3]; hi.kt = h[4]; hi.kr = h[5]; hi.kth = h[6]; hi.kph = h[7];
+        lo.t = l[0]; lo.r = l[1]; lo.th = l[2]; lo.ph = l[3]; lo.kt = l[4]; lo.kr = l[5]; lo.kth = l[6]; lo.kph = l[7];
         sin_cos(hi.th, s, c);
     }
-    __device__ __forceinline__ void store(const IntArgs &A, int64_t id) const
+    __device__ __forceinline__ void store(void *hp, void *lp, int64_t S, int64_t id) const
     {
-        float *H = (float *)A.x, *L = (float *)A.lo;
-        const int64_t S = A.stride;
-        H[0 * S + id] = hi.t; H[1 * S + id] = hi.r; H[2 * S + id] = hi.th; H[3 * S + id] = hi.ph;
-        H[4 * S + id] = hi.kt; H[5 * S + id] = hi.kr; H[6 * S + id] = hi.kth; H[7 * S + id] = hi.kph;
-        L[0 * S + id] = lo.t; L[1 * S + id] = lo.r; L[2 * S + id] = lo.th; L[3 * S + id] = lo.ph;
-        L[4 * S + id] = lo.kt; L[5 * S + id] = lo.kr; L[6 * S + id] = lo.kth; L[7 * S + id] = lo.kph;
+        const float h[8] = {hi.t, hi.r, hi.th, hi.ph, hi.kt, hi.kr, hi.kth, hi.kph};
+        const float l[8] = {lo.t, lo.r, lo.th, lo.ph, lo.kt, lo.kr, lo.kth, lo.kph};
+        Column<float> H((float *)hp, S, id), L((float *)lp, S, id);
+        for (int k = 0; k < 8; ++k) {
+            H.put(h[k]);
+            L.put(l[k]);
+            if (k < 7) {
+                H.next();
+                L.next();
+            }
+        }
     }
     __device__ __forceinline__ State<double> value() const
     {
@@ -471,15 +581,17 @@ template <int P, int PM = kPoleMonitor>
 __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
     const unsigned lane = threadIdx.x & (kWave - 1);
-    const int64_t S = A.stride;
     const bool record_disk = (A.flags & GRAY_RECORD_DISK) != 0;
+    const bool record_mark = A.mark != nullptr;
+    const bool list_out = A.work_out != nullptr;
+    const bool count_done = A.cam_done != nullptr;
 
     bool active = false;
     int64_t id = 0;
     Lane<P> L;
     StepConst<double> K;
     StepConst<float> Kf;
-    double rcap = 0.0;
+    double rcap = 0.0, resc = 0.0;
     float r64 = 0.0f;
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
@@ -520,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 // nq or beyond (and every later one) finds the queue empty.
                 unsigned long long old = 0;
                 if (lane == 0)
-                    old = atomicAdd(A.queue, from_tail ? (unsigned long long)grab << 32 : (unsigned long long)grab);
+                    old = atomicAdd(GRAY_ARG(queue), from_tail ? (unsigned long long)grab << 32 : (unsigned long long)grab);
                 const int64_t h = __builtin_amdgcn_readfirstlane((unsigned)old);
                 const int64_t t = __builtin_amdgcn_readfirstlane((unsigned)(old >> 32));
                 const int64_t end = nq - t;
@@ -540,12 +652,14 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
             const unsigned avail = chunk_end - chunk_next;
             if (avail > 0) {
                 const unsigned rank = lane_rank(idle);
+                const ArgPointers PA = arg_pointers<2>();
+                const int64_t S = A.stride;
                 if (!active && rank < avail) {
                     const unsigned q = chunk_next + rank;
-                    id = (int64_t)A.work_in[q];
-                    if (id >= 0 && A.status[id] == GRAY_RUNNING) {
-                        L.load(A, id);
-                        const DevCam cm = A.cams[A.cam[id]];
+                    id = (int64_t)glob(PA.work_in)[q];
+                    if (id >= 0 && glob(PA.status)[id] == GRAY_RUNNING) {
+                        L.load(PA.x, PA.lo, S, id);
+                        const DevCam cm = PA.cams[glob(PA.cam)[id]];
                         K.B = make_spin(cm.a);
                         K.rbh = cm.rbh;
                         K.step_frac = A.step_frac;
@@ -560,12 +674,19 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                             r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
                         }
                         rcap = cm.rcap;
-                        nsteps = A.steps[id];
+                        resc = A.r_escape;
+                        nsteps = glob(PA.steps)[id];
                         ncall = 0;
-                        ne = A.counters ? A.counters[0 * S + id] : 0;
-                        nr = A.counters ? A.counters[1 * S + id] : 0;
-                        n64 = A.counters ? A.counters[2 * S + id] : 0;
-                        hit = record_disk && A.disk[0 * S + id] != 0.0;
+                        ne = nr = n64 = 0;
+                        if (PA.counters) {
+                            Column<int32_t> C(PA.counters, S, id);
+                            ne = C.get();
+                            C.next();
+                            nr = C.get();
+                            C.next();
+                            n64 = C.get();
+                        }
+                        hit = record_disk && glob(PA.disk)[id] != 0.0;
                         active = true;
                     }
                 }
@@ -574,9 +695,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
             }
             if (exhausted && chunk_next >= chunk_end && ballot(active) == 0ull) {
                 // mark the unused rest of this wave's output span
-                if (A.work_out)
-                    for (unsigned j = span_next + lane; j < span_end; j += kWave) A.work_out[j] = -1;
-                if (A.wave_iters && lane == 0 && iters) atomicAdd(A.wave_iters, iters);
+                if (list_out) {
+                    global_ptr<int32_t> wo = glob(GRAY_ARG(work_out));
+                    for (unsigned j = span_next + lane; j < span_end; j += kWave) wo[j] = -1;
+                }
+                if (unsigned long long *wi = GRAY_ARG(wave_iters))
+                    if (lane == 0 && iters) atomicAdd(wi, iters);
                 break;
             }
         }
@@ -591,26 +715,28 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                     const double f = (kHalfPi - xp.th) / (x.th - xp.th);
                     const double rc = xp.r + f * (x.r - xp.r);
                     // recorder window of the photon's camera, read when needed
-                    const DevCam &cw = A.cams[A.cam[id]];
+                    const DevCam &cw = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
                     if (rc >= cw.disk_rmin && rc <= cw.disk_rmax) {
-                        double E, Lz, Q;
-                        conserved(K.B.a, x, E, Lz, Q);
-                        A.disk[0 * S + id] = rc;
-                        A.disk[1 * S + id] = xp.ph + f * (x.ph - xp.ph);
-                        A.disk[2 * S + id] = disk_redshift(K.B.a, rc, E, Lz);
+                        double E, Lz, Q, sx, cx;
+                        sin_cos<P == GRAY_FP64>(x.th, sx, cx);
+                        conserved_sc(K.B.a, x, sx, cx, E, Lz, Q);
+                        Column<double> D(GRAY_ARG(disk), A.stride, id);
+                        D.put(rc);
+                        D.next();
+                        D.put(xp.ph + f * (x.ph - xp.ph));
+                        D.next();
+                        D.put(disk_redshift(K.B.a, rc, E, Lz));
                         hit = true;
                     }
                 }
                 const double rmark = K.rbh + K.rbh;
-                if (A.mark && xp.r >= rmark && x.r < rmark) {
-                    A.mark[0 * S + id] = xp.t;
-                    A.mark[1 * S + id] = xp.r;
-                    A.mark[2 * S + id] = xp.th;
-                    A.mark[3 * S + id] = xp.ph;
-                    A.mark[4 * S + id] = xp.kt;
-                    A.mark[5 * S + id] = xp.kr;
-                    A.mark[6 * S + id] = xp.kth;
-                    A.mark[7 * S + id] = xp.kph;
+                if (record_mark && xp.r >= rmark && x.r < rmark) {
+                    const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
+                    Column<double> M(GRAY_ARG(mark), A.stride, id);
+                    for (int k = 0; k < 8; ++k) {
+                        M.put(v[k]);
+                        if (k < 7) M.next();
+                    }
                 }
             };
             State<double> x;
@@ -650,17 +776,22 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 nr += (fl >> 1) & 1;
                 if (!finite_state(x)) st = GRAY_NONFINITE;
                 else if (x.r < rcap) st = GRAY_CAPTURED;
-                else if (x.r > A.r_escape && x.kr > 0.0) st = GRAY_ESCAPED;
+                else if (x.r > resc && x.kr > 0.0) st = GRAY_ESCAPED;
                 else if (nsteps >= A.max_steps) st = GRAY_UNFINISHED;
             }
             if (st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps)) {
-                L.store(A, id);
-                A.status[id] = st;
-                A.steps[id] = nsteps;
-                if (A.counters) {
-                    A.counters[0 * S + id] = ne;
-                    A.counters[1 * S + id] = nr;
-                    A.counters[2 * S + id] = n64;
+                const ArgPointers PA = arg_pointers<1>();
+                const int64_t S = A.stride;
+                L.store(PA.x, PA.lo, S, id);
+                glob(PA.status)[id] = st;
+                glob(PA.steps)[id] = nsteps;
+                if (PA.counters) {
+                    Column<int32_t> C(PA.counters, S, id);
+                    C.put(ne);
+                    C.next();
+                    C.put(nr);
+                    C.next();
+                    C.put(n64);
                 }
                 stop_now = true;
                 keep = st == GRAY_RUNNING;
@@ -669,7 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
         }
 
         // Wave-uniform bookkeeping of the photons that stopped this iteration.
-        if (A.work_out) {
+        if (list_out) {
             // Photons still running go on the next work list, written into
             // the wave's reserved span; when it fills up the rest continues
             // in a fresh span of kSpan slots, so the only unused slots are
@@ -680,11 +811,11 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 const unsigned room = span_end - span_next;
                 unsigned fresh = 0;
                 if (cnt > room) {
-                    if (lane == 0) fresh = atomicAdd(A.work_out_count, kSpan);
+                    if (lane == 0) fresh = atomicAdd(GRAY_ARG(work_out_count), kSpan);
                     fresh = __builtin_amdgcn_readfirstlane(fresh);
                 }
                 const unsigned r = lane_rank(m);
-                if (keep) A.work_out[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
+                if (keep) glob(GRAY_ARG(work_out))[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
                 if (cnt > room) {
                     span_next = fresh + (cnt - room);
                     span_end = fresh + kSpan;
@@ -693,19 +824,19 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 }
             }
         }
-        if (A.cam_done) {
+        if (count_done) {
             // Completion count per camera: one atomic per wave when the
             // photons that finished share a camera.
             const bool fin = stop_now && !keep;
             const uint64_t mf = ballot(fin);
             if (mf) {
-                const int32_t c = fin ? A.cam[id] : -1;
+                const int32_t c = fin ? glob(GRAY_ARG(cam))[id] : -1;
                 const unsigned lead = (unsigned)(__ffsll((long long)mf) - 1);
                 const int32_t cl = __shfl(c, (int)lead, kWave);
                 if (ballot(fin && c != cl) == 0ull) {
-                    if (lane == lead) atomicAdd(&A.cam_done[cl], (unsigned)__popcll(mf));
+                    if (lane == lead) atomicAdd(GRAY_ARG(cam_done) + cl, (unsigned)__popcll(mf));
                 } else if (fin) {
-                    atomicAdd(&A.cam_done[c], 1u);
+                    atomicAdd(GRAY_ARG(cam_done) + c, 1u);
                 }
             }
         }

@@ -616,16 +616,22 @@ GRAY_HD void camera_state(double a, double D, double incl, double alpha, double 
     x.kph = -pph;
 }
 
-// E = -p_t, L = p_phi, Q = p_th^2 + cos^2 (L^2 / sin^2 - a^2 E^2) of p = -k.
-GRAY_HD void conserved(double a, const State<double> &x, double &E, double &L, double &Q)
+// E = -p_t, L = p_phi, Q = p_th^2 + cos^2 (L^2 / sin^2 - a^2 E^2) of p = -k,
+// given s, c = sin, cos of x.th.
+GRAY_HD void conserved_sc(double a, const State<double> &x, double s, double c, double &E, double &L, double &Q)
 {
-    double s, c;
-    sincos(x.th, &s, &c);
     const Metric<double> g = metric(a, a * a, x.r, s, c);
     E = g.tt * x.kt + g.tph * x.kph;
     L = -(g.tph * x.kt + g.phph * x.kph);
     const double pth = -g.thth * x.kth;
     Q = pth * pth + c * c * (L * L / (s * s) - a * a * E * E);
+}
+
+GRAY_HD void conserved(double a, const State<double> &x, double &E, double &L, double &Q)
+{
+    double s, c;
+    sincos(x.th, &s, &c);
+    conserved_sc(a, x, s, c, E, L, Q);
 }
 
 // Redshift of light from a prograde Keplerian emitter at radius rc in the
