@@ -323,10 +323,41 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
         d = cons[6:9, sel]
         drift[name] = {q: np.percentile(d, pq, axis=1).tolist()
                        for q, pq in (("p50", 50), ("p99", 99), ("max", 100))} if d.size else {}
+    tail = longest_alone(G, W, torch, np, b, params)
     return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
             "total_steps": total_steps, "status": np.bincount(status, minlength=5).tolist(),
             "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n,
-            "lane_efficiency": lane_eff}
+            "lane_efficiency": lane_eff, "tail": tail}
+
+
+def longest_alone(G, W, torch, np, b, params, reps: int = 3) -> dict:
+    """The launch's floor: its longest photon traced alone (a one-photon work
+    list, so one wave on an otherwise idle GPU). A launch cannot end before
+    that photon does, and the photon cannot run faster than alone."""
+    steps = b.steps[: b.n].cpu().numpy()
+    pid = int(np.argmax(steps))
+    wl = [torch.zeros(G.GRAY_WORKLIST_SLACK + 64, dtype=torch.int32, device="cuda") for _ in range(2)]
+    wc = torch.zeros(2, dtype=torch.int32, device="cuda")
+    pp = G.params_struct(params)
+    pp.flags |= G.GRAY_WORKLIST
+    st = G.gray_state(b.state.x, b.state.lo, b.state.status, b.state.steps, b.state.cam, None, None, None,
+                      b.n, b.stride, wl[0].data_ptr(), wl[1].data_ptr(), wc.data_ptr(), wc.data_ptr() + 4)
+    ts = []
+    for _ in range(reps):
+        b.camera_init()
+        wl[0][0] = pid
+        wc.zero_()
+        wc[0] = 1
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        G.gray_integrate(b.cam_arr, 1, pp, st, b.ws_ptr, b.ws_bytes, G.current_stream())
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    alone_steps = int(b.steps[pid].item())
+    return {"photon": pid, "steps": int(steps[pid]), "alone_steps": alone_steps, "alone_ms": min(ts),
+            "alone_us_per_step": min(ts) * 1e3 / max(1, alone_steps)}
 
 
 def main():
@@ -387,6 +418,9 @@ def main():
         "status_counts": head["status"],
         "euler_fallback_steps": head["euler_steps"],
         "lane_efficiency": head["lane_efficiency"],
+        # the launch's floor: its longest photon alone on the GPU
+        "longest_photon": dict(head["tail"], launch_ms=head["integrate_ms"],
+                               floor_fraction=head["tail"]["alone_ms"] / head["integrate_ms"]),
         "drift_ELQ": head["drift"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(args.precision),
