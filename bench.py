@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
     ap.add_argument("--no-ring", action="store_true", help="skip the photon-ring study")
     ap.add_argument("--no-pole", action="store_true", help="skip the pole-treatment ablation")
+    ap.add_argument("--no-floor", action="store_true",
+                    help="skip tracing the longest photon alone (keeps a profile's integrator launches all 512^2 ones)")
     ap.add_argument("--no-nsweep", action="store_true",
                     help="skip the grid-projection run time versus number of rays")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -282,7 +284,7 @@ def ring_study(np) -> dict:
     return timing
 
 
-def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
+def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int, floor: bool = True) -> dict:
     """Time `steps` passes (camera_init + integrate + classify) after `warmup`."""
     params = W.Params(precision=prec)
     b = G.Batch([cam], params)
@@ -323,7 +325,7 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int) -> dict:
         d = cons[6:9, sel]
         drift[name] = {q: np.percentile(d, pq, axis=1).tolist()
                        for q, pq in (("p50", 50), ("p99", 99), ("max", 100))} if d.size else {}
-    tail = longest_alone(G, W, torch, np, b, params)
+    tail = longest_alone(G, W, torch, np, b, params) if floor else None
     return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
             "total_steps": total_steps, "status": np.bincount(status, minlength=5).tolist(),
             "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n,
@@ -384,9 +386,9 @@ def main():
         del src, dst
     cam = W.C2
     print("bench: timing the 512x512 workload", file=sys.stderr, flush=True)
-    head = measure(G, W, torch, np, cam, args.precision, args.steps, args.warmup)
+    head = measure(G, W, torch, np, cam, args.precision, args.steps, args.warmup, not args.no_floor)
     other_prec = "fp32c" if args.precision == "fp64" else "fp64"
-    other = measure(G, W, torch, np, cam, other_prec, args.steps, args.warmup)
+    other = measure(G, W, torch, np, cam, other_prec, args.steps, args.warmup, False)
     t64 = head["integrate_ms"] if args.precision == "fp64" else other["integrate_ms"]
     t32 = other["integrate_ms"] if args.precision == "fp64" else head["integrate_ms"]
 
@@ -419,8 +421,9 @@ def main():
         "euler_fallback_steps": head["euler_steps"],
         "lane_efficiency": head["lane_efficiency"],
         # the launch's floor: its longest photon alone on the GPU
-        "longest_photon": dict(head["tail"], launch_ms=head["integrate_ms"],
-                               floor_fraction=head["tail"]["alone_ms"] / head["integrate_ms"]),
+        "longest_photon": (dict(head["tail"], launch_ms=head["integrate_ms"],
+                                floor_fraction=head["tail"]["alone_ms"] / head["integrate_ms"])
+                           if head["tail"] else None),
         "drift_ELQ": head["drift"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(args.precision),
