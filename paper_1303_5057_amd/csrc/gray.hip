@@ -766,20 +766,19 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 x = F.value();
                 if (fl >= 0) record(xp, x);
             }
+            // status after the step, taken with selects (no per-lane branch)
+            const bool ok = fl >= 0;
+            nsteps += ok;
+            ncall += ok;
+            ne += ok ? (fl & 1) : 0;
+            nr += ok ? ((fl >> 1) & 1) : 0;
             int32_t st = GRAY_RUNNING;
-            if (fl < 0) {
-                st = GRAY_NONFINITE;
-            } else {
-                ++nsteps;
-                ++ncall;
-                ne += fl & 1;
-                nr += (fl >> 1) & 1;
-                if (!finite_state(x)) st = GRAY_NONFINITE;
-                else if (x.r < rcap) st = GRAY_CAPTURED;
-                else if (x.r > resc && x.kr > 0.0) st = GRAY_ESCAPED;
-                else if (nsteps >= A.max_steps) st = GRAY_UNFINISHED;
-            }
-            if (st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps)) {
+            st = nsteps >= A.max_steps ? GRAY_UNFINISHED : st;
+            st = (x.r > resc && x.kr > 0.0) ? GRAY_ESCAPED : st;
+            st = x.r < rcap ? GRAY_CAPTURED : st;
+            st = (!ok || !finite_state(x)) ? GRAY_NONFINITE : st;
+            const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
+            if (__builtin_expect(any_lane(stop), 0) && stop) {
                 const ArgPointers PA = arg_pointers<1>();
                 const int64_t S = A.stride;
                 L.store(PA.x, PA.lo, S, id);

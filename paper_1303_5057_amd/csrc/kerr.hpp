@@ -56,6 +56,19 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
 constexpr double kHalfPi = 0.5 * 3.14159265358979323846;
 
+// True when p holds on some lane of the wave (on the host: p). Branching on
+// it costs a wave one scalar branch; a per-lane branch also saves, masks
+// and restores the execution mask, and a wave alone on its SIMD waits tens
+// of cycles for each, so rare cases are tested with any_lane first.
+GRAY_HD bool any_lane(bool p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_ballot_w64(p) != 0ull;
+#else
+    return p;
+#endif
+}
+
 // ------------------------------------------------------------ FP64 primitives
 // Reciprocal: the hardware estimate refined by two Newton-Raphson steps
 // (y <- y + y (1 - x y)), accurate to about one ulp for the magnitudes met
@@ -182,17 +195,21 @@ template <bool SGPR = true>
 GRAY_HD void sin_cos(double x, double &s, double &c) { sincos_full<SGPR>(x, s, c); }
 
 // sin and cos of th = th0 + d from those of th0 (angle addition with the
-// small-angle series); falls back to the full evaluation when |d| > 1/16.
+// small-angle series); the full evaluation where |d| > 1/16 (rare: the
+// stage offsets obey |d| <= Delta to first order).
 template <bool SGPR = true>
 GRAY_HD void shift_sincos(double s0, double c0, double d, double th, double &s, double &c)
 {
-    if (fabs(d) <= 0.0625) {
-        double sd, cd;
-        sincos_small<SGPR>(d, sd, cd);
-        s = fma(s0, cd, c0 * sd);
-        c = fma(c0, cd, -(s0 * sd));
-    } else {
-        sincos_full<SGPR>(th, s, c);
+    double sd, cd;
+    sincos_small<SGPR>(d, sd, cd);
+    s = fma(s0, cd, c0 * sd);
+    c = fma(c0, cd, -(s0 * sd));
+    const bool wide = !(fabs(d) <= 0.0625);
+    if (__builtin_expect(any_lane(wide), 0)) {
+        double sf, cf;
+        sincos_full<SGPR>(th, sf, cf);
+        s = wide ? sf : s;
+        c = wide ? cf : c;
     }
 }
 
@@ -451,7 +468,9 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&obser
     const T d2 = akr + akr;
     const bool second = (x.kr != T(0)) && (n2 * D1 < d2 * n1);
     const T h = second ? quot(n2, d2) : quot(n1, D1);
-    if (!(h > T(0) && h < T(INFINITY))) return -1;
+    const bool hbad = !(h > T(0) && h < T(INFINITY));
+    if (__builtin_expect(any_lane(hbad), 0))
+        if (hbad) return -1;
     const T hh = T(0.5) * h;
 
     // The stage derivatives are summed as they come, k1 + 2 k2 + 2 k3 + k4
@@ -481,30 +500,32 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&obser
 
     int flags = 0;
     step_sin_cos<SC>(xn.th, sy, cy);
+    bool viol = false;
     if constexpr (PM == kPoleMonitor) {
         const Metric<T> g = metric(K.B.a, K.B.a2, xn.r, sy, cy);
-        if (xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps)) {
-            xn = axpy(x, h * K.euler_inv, k1);
-            flags |= 1;
-        }
+        viol = xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps);
     } else if constexpr (PM == kPoleEulerCrossing) {
-        if (xn.th > T(kPi) || xn.th < T(0)) {
-            xn = axpy(x, h, k1);
+        viol = xn.th > T(kPi) || xn.th < T(0);
+    }
+    // The fallback and the remap, entered only when some lane needs one.
+    if (__builtin_expect(any_lane(viol || xn.th > T(kPi) || xn.th < T(0)), 0)) {
+        if (viol) {
+            xn = axpy(x, PM == kPoleMonitor ? h * K.euler_inv : h, k1);
             flags |= 1;
         }
+        if (xn.th > T(kPi)) {
+            xn.th = T(kTwoPi) - xn.th;
+            xn.ph = xn.ph + T(kPi);
+            xn.kth = -xn.kth;
+            flags |= 2;
+        } else if (xn.th < T(0)) {
+            xn.th = -xn.th;
+            xn.ph = xn.ph - T(kPi);
+            xn.kth = -xn.kth;
+            flags |= 2;
+        }
+        if (flags) step_sin_cos<SC>(xn.th, sy, cy);
     }
-    if (xn.th > T(kPi)) {
-        xn.th = T(kTwoPi) - xn.th;
-        xn.ph = xn.ph + T(kPi);
-        xn.kth = -xn.kth;
-        flags |= 2;
-    } else if (xn.th < T(0)) {
-        xn.th = -xn.th;
-        xn.ph = xn.ph - T(kPi);
-        xn.kth = -xn.kth;
-        flags |= 2;
-    }
-    if (flags) step_sin_cos<SC>(xn.th, sy, cy);
     observe(x, xn);
     x = xn;
     s = sy;
