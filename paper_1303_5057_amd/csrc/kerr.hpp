@@ -507,24 +507,23 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&obser
     } else if constexpr (PM == kPoleEulerCrossing) {
         viol = xn.th > T(kPi) || xn.th < T(0);
     }
-    // The fallback and the remap, entered only when some lane needs one.
+    // The fallback and the remap, entered only when some lane needs one
+    // (the remap and the new sin/cos by selects: a photon locked into the
+    // fallback takes this block on most steps).
     if (__builtin_expect(any_lane(viol || xn.th > T(kPi) || xn.th < T(0)), 0)) {
         if (viol) {
             xn = axpy(x, PM == kPoleMonitor ? h * K.euler_inv : h, k1);
             flags |= 1;
         }
-        if (xn.th > T(kPi)) {
-            xn.th = T(kTwoPi) - xn.th;
-            xn.ph = xn.ph + T(kPi);
-            xn.kth = -xn.kth;
-            flags |= 2;
-        } else if (xn.th < T(0)) {
-            xn.th = -xn.th;
-            xn.ph = xn.ph - T(kPi);
-            xn.kth = -xn.kth;
-            flags |= 2;
-        }
-        if (flags) step_sin_cos<SC>(xn.th, sy, cy);
+        const bool up = xn.th > T(kPi), down = xn.th < T(0);
+        xn.th = up ? T(kTwoPi) - xn.th : (down ? -xn.th : xn.th);
+        xn.ph = up ? xn.ph + T(kPi) : (down ? xn.ph - T(kPi) : xn.ph);
+        xn.kth = (up || down) ? -xn.kth : xn.kth;
+        flags |= (up || down) ? 2 : 0;
+        T sf, cf;
+        step_sin_cos<SC>(xn.th, sf, cf);
+        sy = flags ? sf : sy;
+        cy = flags ? cf : cy;
     }
     observe(x, xn);
     x = xn;

@@ -11,7 +11,7 @@ import pytest
 
 import analytic
 import oracle
-from parity import compare_prec, run_gpu, run_oracle
+from parity import compare_prec, pixel_ab, run_gpu, run_oracle
 from paper_1303_5057_amd import gray as G
 from paper_1303_5057_amd import workloads as W
 
@@ -229,3 +229,37 @@ def test_disk_recorder(prec):
     tol = 1e-9 if prec == "fp64" else 1e-3
     assert np.allclose(g.disk.T[m], o.disk[m], rtol=tol, atol=tol)
     assert np.all(g.disk[0, hit_g] >= oracle.r_isco(cam.a)) and np.all(g.disk[0, hit_g] <= 50.0)
+
+
+def _stage_offsets(cam, p, ids):
+    """|theta offsets| of the three RK4 stages along oracle paths of the
+    listed rays (step rule and stage states as in Sec. 2)."""
+    rbh = 1.0 + np.sqrt(1.0 - cam.a * cam.a)
+    al, be = pixel_ab(cam, np.asarray(ids))
+    out = []
+    for a_, b_ in zip(al, be):
+        x0 = oracle.camera(cam.a, cam.r_obs, cam.incl, a_, b_)
+        _, path, _ = oracle.trace_path(oracle.make_params(step_frac=p.step_frac), cam.a, x0)
+        for x in np.asarray(path)[:-1]:
+            h = oracle.step_size(rbh, p.step_frac, x)
+            k1 = np.asarray(oracle.rhs(cam.a, x))
+            k2 = np.asarray(oracle.rhs(cam.a, x + 0.5 * h * k1))
+            k3 = np.asarray(oracle.rhs(cam.a, x + 0.5 * h * k2))
+            out.append(max(abs(0.5 * h * k1[2]), abs(0.5 * h * k2[2]), abs(h * k3[2])))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_coarse_steps_exercise_full_stage_angles(prec):
+    """With Delta = 1/2 the theta offsets of the RK4 stages exceed the
+    small-angle series' range (1/16) on many steps, so the stages take the
+    full sin/cos there (a wave-wide branch in the kernels); the result still
+    matches the oracle under the usual rules."""
+    cam = W.Camera(0.9, 1000.0, np.radians(60.0), 40, 36, -8.0, 8.0, -8.0, 8.0)
+    p = W.Params(precision=prec, step_frac=0.5)
+    d = _stage_offsets(cam, p, [5, 300, 777, 1111])
+    assert np.mean(d > 0.0625) > 0.05, np.mean(d > 0.0625)
+    g = run_gpu([cam], p)
+    o = run_oracle(cam, p)
+    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec), prec,
+           allow=2 * STEP_MISMATCH[prec])
