@@ -410,6 +410,29 @@ GRAY_HD bool xi_violated(const Metric<T> &g, T kt, T kr, T kth, T kph, T eps)
     return fabs(num + den) > eps * fabs(den);
 }
 
+// The same test at (r, theta) given sin/cos of theta, free of divisions: the
+// metric components times Sigma Delta (a factor that changes neither side
+// of |N + g_tt kt^2| > eps |g_tt kt^2|) are polynomials,
+//   g_tt Sigma Delta = (2 r - Sigma) Delta,   g_tph Sigma Delta = -2 a r sin^2 Delta,
+//   g_rr Sigma Delta = Sigma^2,   g_thth Sigma Delta = Sigma^2 Delta,
+//   g_phph Sigma Delta = (rho^2 Sigma + 2 a^2 r sin^2) sin^2 Delta.
+template <class T>
+GRAY_HD bool xi_violated_at(T a, T a2, T r, T s, T c, T kt, T kr, T kth, T kph, T eps)
+{
+    const T s2 = s * s;
+    const T r2 = r * r;
+    const T sig = fma(a2, c * c, r2);
+    const T del = fma(r, r - T(2), a2);
+    const T sig2 = sig * sig;
+    const T ar2 = (a + a) * r;                           // 2 a r
+    const T phph = fma(ar2 * a, s2, (r2 + a2) * sig);    // rho^2 Sigma + 2 a^2 r sin^2
+    T inner = fma(sig2, kth * kth, phph * (s2 * kph) * kph);
+    inner = fma(-(ar2 + ar2) * (s2 * kt), kph, inner);
+    const T num = fma(del, inner, sig2 * (kr * kr));
+    const T den = ((r + r - sig) * del) * (kt * kt);
+    return fabs(num + den) > eps * fabs(den);
+}
+
 // Treatment of the polar axis (values of gray_pole_mode): the production
 // null-condition monitor, the earlier Euler step on pole crossings, or none.
 constexpr int kPoleMonitor = 0, kPoleEulerCrossing = 1, kPoleNone = 2;
@@ -502,8 +525,7 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&obser
     step_sin_cos<SC>(xn.th, sy, cy);
     bool viol = false;
     if constexpr (PM == kPoleMonitor) {
-        const Metric<T> g = metric(K.B.a, K.B.a2, xn.r, sy, cy);
-        viol = xi_violated(g, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps);
+        viol = xi_violated_at(K.B.a, K.B.a2, xn.r, sy, cy, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps);
     } else if constexpr (PM == kPoleEulerCrossing) {
         viol = xn.th > T(kPi) || xn.th < T(0);
     }
@@ -588,8 +610,7 @@ GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<floa
           isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph)))
         return -2;
     sin_cos(nh.th, sy, cy);
-    const Metric<float> g = metric(K.B.a, K.B.a2, nh.r, sy, cy);
-    if (xi_violated(g, nh.kt, nh.kr, nh.kth, nh.kph, guard)) return -2;
+    if (xi_violated_at(K.B.a, K.B.a2, nh.r, sy, cy, nh.kt, nh.kr, nh.kth, nh.kph, guard)) return -2;
     hi = nh;
     lo = nl;
     s = sy;
