@@ -401,19 +401,10 @@ GRAY_HD Metric<T> metric(T a, T a2, T r, T s, T c)
     return g;
 }
 
-// Null-condition test of eq. (4) without the division:
-// |xi + 1| > eps  <=>  |N + g_tt kt^2| > eps |g_tt kt^2|, N the numerator of xi.
-template <class T>
-GRAY_HD bool xi_violated(const Metric<T> &g, T kt, T kr, T kth, T kph, T eps)
-{
-    const T den = g.tt * kt * kt;
-    const T num = g.rr * kr * kr + g.phph * kph * kph + g.thth * kth * kth + T(2) * g.tph * kt * kph;
-    return fabs(num + den) > eps * fabs(den);
-}
-
-// The same test at (r, theta) given sin/cos of theta, free of divisions: the
-// metric components times Sigma Delta (a factor that changes neither side
-// of |N + g_tt kt^2| > eps |g_tt kt^2|) are polynomials,
+// Null-condition test of eq. (4) at (r, theta) given sin/cos of theta, free
+// of divisions: |xi + 1| > eps  <=>  |N + g_tt kt^2| > eps |g_tt kt^2| with N
+// the numerator of xi, and the metric components times Sigma Delta (a factor
+// that changes neither side) are polynomials,
 //   g_tt Sigma Delta = (2 r - Sigma) Delta,   g_tph Sigma Delta = -2 a r sin^2 Delta,
 //   g_rr Sigma Delta = Sigma^2,   g_thth Sigma Delta = Sigma^2 Delta,
 //   g_phph Sigma Delta = (rho^2 Sigma + 2 a^2 r sin^2) sin^2 Delta.
