@@ -75,7 +75,7 @@ typedef enum {
     GRAY_EINVAL = -1,       /* bad argument; nothing was enqueued            */
     GRAY_EDEVICE = -2,      /* HIP runtime or launch failure                 */
     GRAY_EWORKSPACE = -3,   /* workspace NULL or smaller than required       */
-    GRAY_EUNSUPPORTED = -4  /* valid request this build cannot serve         */
+    GRAY_EUNSUPPORTED = -4  /* valid request the library does not serve     */
 } gray_err;
 
 typedef enum {
