@@ -264,13 +264,16 @@ GRAY_HD void sin_cos(float x, float &s, float &c) { sincos_full(x, s, c); }
 
 GRAY_HD void shift_sincos(float s0, float c0, float d, float th, float &s, float &c)
 {
-    if (fabsf(d) <= 0.0625f) {
-        float sd, cd;
-        sincos_small(d, sd, cd);
-        s = fma(s0, cd, c0 * sd);
-        c = fma(c0, cd, -(s0 * sd));
-    } else {
-        sincos_full(th, s, c);
+    float sd, cd;
+    sincos_small(d, sd, cd);
+    s = fma(s0, cd, c0 * sd);
+    c = fma(c0, cd, -(s0 * sd));
+    const bool wide = !(fabsf(d) <= 0.0625f);
+    if (__builtin_expect(any_lane(wide), 0)) {
+        float sf, cf;
+        sincos_full(th, sf, cf);
+        s = wide ? sf : s;
+        c = wide ? cf : c;
     }
 }
 
@@ -575,7 +578,7 @@ GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<floa
     const float d2 = akr + akr;
     const bool second = (hi.kr != 0.0f) && (n2 * D1 < d2 * n1);
     const float h = second ? quot(n2, d2) : quot(n1, D1);
-    if (!(h > 0.0f && h < INFINITY)) return -2;
+    const bool hbad = !(h > 0.0f && h < INFINITY);
     const float hh = 0.5f * h;
 
     State<float> k1, k2, k3, k4, y;
@@ -597,12 +600,15 @@ GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<floa
     GRAY_C32(t); GRAY_C32(r); GRAY_C32(th); GRAY_C32(ph);
     GRAY_C32(kt); GRAY_C32(kr); GRAY_C32(kth); GRAY_C32(kph);
 #undef GRAY_C32
-    if (!(nh.th >= 0.0f && nh.th <= float(kPi))) return -2;
-    if (!(isfinite(nh.t) && isfinite(nh.r) && isfinite(nh.ph) && isfinite(nh.kt) &&
-          isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph)))
-        return -2;
+    // every rejection in one wave-wide test (an invalid h computes the
+    // stages on non-finite values and is rejected here)
     sin_cos(nh.th, sy, cy);
-    if (xi_violated_at(K.B.a, K.B.a2, nh.r, sy, cy, nh.kt, nh.kr, nh.kth, nh.kph, guard)) return -2;
+    const bool reject = hbad || !(nh.th >= 0.0f && nh.th <= float(kPi)) ||
+                        !(isfinite(nh.t) && isfinite(nh.r) && isfinite(nh.ph) && isfinite(nh.kt) &&
+                          isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph)) ||
+                        xi_violated_at(K.B.a, K.B.a2, nh.r, sy, cy, nh.kt, nh.kr, nh.kth, nh.kph, guard);
+    if (__builtin_expect(any_lane(reject), 0))
+        if (reject) return -2;
     hi = nh;
     lo = nl;
     s = sy;
