@@ -709,9 +709,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
         iters += ballot(active) != 0ull;
         if (active) {
             // Equatorial-crossing recorder and 2 r_bh mark of one accepted
-            // step from xp to x.
+            // step from xp to x (each a rare event, tested wave-wide first).
             auto record = [&](const State<double> &xp, const State<double> &x) {
-                if (record_disk && !hit && (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0) {
+                const bool cross = record_disk && !hit && (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0;
+                if (record_disk && __builtin_expect(any_lane(cross), 0) && cross) {
                     const double f = (kHalfPi - xp.th) / (x.th - xp.th);
                     const double rc = xp.r + f * (x.r - xp.r);
                     // recorder window of the photon's camera, read when needed
@@ -730,7 +731,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                     }
                 }
                 const double rmark = K.rbh + K.rbh;
-                if (record_mark && xp.r >= rmark && x.r < rmark) {
+                const bool inward = xp.r >= rmark && x.r < rmark;
+                if (record_mark && __builtin_expect(any_lane(inward), 0) && inward) {
                     const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
                     Column<double> M(GRAY_ARG(mark), A.stride, id);
                     for (int k = 0; k < 8; ++k) {
