@@ -342,8 +342,10 @@ def longest_alone(G, W, torch, np, b, params, reps: int = 3) -> dict:
     wc = torch.zeros(2, dtype=torch.int32, device="cuda")
     pp = G.params_struct(params)
     pp.flags |= G.GRAY_WORKLIST
-    st = G.gray_state(b.state.x, b.state.lo, b.state.status, b.state.steps, b.state.cam, None, None, None,
-                      b.n, b.stride, wl[0].data_ptr(), wl[1].data_ptr(), wc.data_ptr(), wc.data_ptr() + 4)
+    # the launch's own counters and mark buffers, so the photon runs the same recorders
+    st = G.gray_state(b.state.x, b.state.lo, b.state.status, b.state.steps, b.state.cam, b.state.counters,
+                      b.state.mark, None, b.n, b.stride, wl[0].data_ptr(), wl[1].data_ptr(), wc.data_ptr(),
+                      wc.data_ptr() + 4)
     ts = []
     for _ in range(reps):
         b.camera_init()
