@@ -115,23 +115,29 @@ def schw_turning_point(b):
 
 def schw_sweep(b, r_from, r_to=None, through_turning=True):
     """Total orbital angle swept by a Schwarzschild null ray of impact parameter
-    b, moving in from r_from, through the turning point and out to r_to."""
+    b > sqrt(27), moving in from r_from, through the turning point and out to
+    r_to (through_turning=False: from r_from in to r_to only).
+
+    With u = 1/r the orbit equation is dpsi/du = 1 / sqrt(P(u)),
+    P(u) = 2 u^3 - u^2 + 1/b^2, whose smallest positive root u0 = 1/r_min is
+    the turning point. Dividing out that root, P(u) = (u0 - u) S(u) with
+    S(u) = -(2 u^2 + (2 u0 - 1) u + u0 (2 u0 - 1)) > 0 on [0, u0], and the
+    substitution u = u0 - s^2 turns every leg into the integral of the
+    smooth 2 / sqrt(S(u0 - s^2)) over s, with no end-point singularity and no
+    cancellation near the turning point."""
+    u0 = 1.0 / schw_turning_point(b)
+    c1, c0 = 2.0 * u0 - 1.0, u0 * (2.0 * u0 - 1.0)
+
     def leg(r_hi, r_lo):
-        # u = 1/r; dpsi/du = 1 / sqrt(1/b^2 - u^2 + 2 u^3)
-        u_lo, u_hi = 1.0 / r_hi, 1.0 / r_lo
-        f = lambda u: 1.0 / np.sqrt(max(1.0 / (b * b) - u * u + 2.0 * u ** 3, 1e-300))
-        if through_turning:
-            # substitute u = u_hi - s^2 to remove the inverse-square-root end point
-            g = lambda s: 2.0 * s * f(u_hi - s * s)
-            val, _ = integrate.quad(g, 0.0, np.sqrt(u_hi - u_lo), epsabs=1e-14, epsrel=1e-13,
-                                    limit=400)
-            return val
-        val, _ = integrate.quad(f, u_lo, u_hi, epsabs=1e-14, epsrel=1e-13, limit=400)
+        s_lo = np.sqrt(max(u0 - 1.0 / r_lo, 0.0))   # the inner end (larger u)
+        s_hi = np.sqrt(u0 - 1.0 / r_hi)
+        g = lambda s: 2.0 / np.sqrt(-(2.0 * (u0 - s * s) ** 2 + c1 * (u0 - s * s) + c0))
+        val, _ = integrate.quad(g, s_lo, s_hi, epsabs=1e-14, epsrel=1e-13, limit=400)
         return val
 
     if not through_turning:
         return leg(r_from, r_to)
-    rmin = schw_turning_point(b)
+    rmin = 1.0 / u0
     total = leg(r_from, rmin)
     if r_to is not None:
         total += leg(r_to, rmin)

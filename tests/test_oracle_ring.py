@@ -122,3 +122,84 @@ def test_oracle_edge_is_a_boundary(orc):
         st = R.ray_status(a, 1000.0, incl, t, idx, nr, r_lo, r_hi)
         assert np.all(st[idx < n] == orc.CAPTURED)
         assert np.all(st[idx >= n] == orc.ESCAPED)
+
+
+def _golden_fits():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.json")
+    return json.load(open(path))["photon_ring_fits"]
+
+
+def _fit_from_table(t, a, incl_deg):
+    """<R> and A evaluated from the printed coefficients in the golden table."""
+    m = t["mean_radius"]
+    r0 = sum(c * a ** k for k, c in enumerate(m["R_0_coeffs_of_a_powers_0_to_3"]))
+    q = m["R_1"]
+    r1 = (q["c"] - q["num"] / ((a - q["shift"]) ** 2 + q["offset"])) * q["scale"]
+    mean = r0 + r1 * math.cos(math.radians(m["freq"] * incl_deg - m["phase_deg"]))
+    s = t["asymmetry"]
+    a0 = sum(c * a ** p for c, p in s["A_0_coeff_power_pairs"])
+    n = sum(c * (1.0 - a) ** p for c, p in s["n_coeff_power_pairs"])
+    return mean, a0 * math.sin(math.radians(incl_deg)) ** n
+
+
+FIT_SPINS = [1.0 - 10.0 ** (-j / 5.0) for j in range(16)] + [0.3, 0.9017, 0.95]
+FIT_INCLS = list(range(0, 91, 5)) + [17, 33.3]
+
+
+def test_fits_match_printed_coefficients():
+    """Both copies of the Sec. 4 fits (the oracle's and the product's ring
+    module) equal the fits rebuilt from the coefficients printed in the
+    paper (tests/golden/paper_values.json) on the study's (a, i) grid."""
+    from paper_1303_5057_amd import ring as GR
+    t = _golden_fits()
+    for a in FIT_SPINS:
+        for i in FIT_INCLS:
+            mean, asym = _fit_from_table(t, a, i)
+            assert R.fit_mean_radius(a, i) == pytest.approx(mean, rel=1e-13, abs=1e-13)
+            assert GR.paper_fit_mean_radius(a, i) == pytest.approx(mean, rel=1e-13, abs=1e-13)
+            assert R.fit_asymmetry(a, i) == pytest.approx(asym, rel=1e-13, abs=1e-15)
+            assert GR.paper_fit_asymmetry(a, i) == pytest.approx(asym, rel=1e-13, abs=1e-15)
+
+
+def _perturbations(t):
+    """Copies of the table with one printed coefficient changed in its last
+    printed digit (e.g. 0.567 -> 0.568)."""
+    import copy
+
+    def bump(v):
+        txt = repr(float(v))
+        dec = len(txt.split(".")[1]) if "." in txt and not txt.endswith(".0") else 0
+        return v + 10.0 ** (-dec)
+
+    paths = [("mean_radius", "R_0_coeffs_of_a_powers_0_to_3", k) for k in range(4)]
+    paths += [("mean_radius", "R_1", f) for f in ("c", "num", "shift", "offset")]
+    paths += [("mean_radius", "freq", None), ("mean_radius", "phase_deg", None)]
+    paths += [("asymmetry", "A_0_coeff_power_pairs", (k, j)) for k in range(3) for j in range(2)]
+    paths += [("asymmetry", "n_coeff_power_pairs", (k, j)) for k in range(2) for j in range(2)]
+    for top, key, sub in paths:
+        u = copy.deepcopy(t)
+        node = u[top]
+        if sub is None:
+            node[key] = bump(node[key])
+        elif isinstance(sub, tuple):
+            node[key][sub[0]][sub[1]] = bump(node[key][sub[0]][sub[1]])
+        else:
+            node[key][sub] = bump(node[key][sub])
+        yield (top, key, sub), u
+
+
+def test_fit_check_detects_a_one_digit_change():
+    """The comparison above is sensitive: changing any one printed
+    coefficient by one unit in its last digit moves <R> or A by more than the
+    tolerance somewhere on the grid."""
+    t = _golden_fits()
+    for where, u in _perturbations(t):
+        worst = 0.0
+        for a in FIT_SPINS:
+            for i in FIT_INCLS:
+                m0, a0 = _fit_from_table(t, a, i)
+                m1, a1 = _fit_from_table(u, a, i)
+                worst = max(worst, abs(m1 - m0) / max(abs(m0), 1e-300), abs(a1 - a0) / max(abs(a0), 1e-15))
+        assert worst > 1e-9, where
