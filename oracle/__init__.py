@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("euler_div", ctypes.c_double), ("disk_rmin", ctypes.c_double),
                 ("disk_rmax", ctypes.c_double), ("max_steps", ctypes.c_int32),
                 ("record_disk", ctypes.c_int32), ("pole_mode", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("metric", ctypes.c_int32), ("eps3", ctypes.c_double)]
 
 
 class CameraT(ctypes.Structure):
@@ -55,13 +55,14 @@ class CameraT(ctypes.Structure):
 
 
 POLE_MONITOR, POLE_EULER_CROSSING, POLE_NONE = 0, 1, 2
+METRIC_KERR, METRIC_JP = 0, 1
 
 
 def make_params(step_frac=1.0 / 32, horizon_eps=1e-3, r_escape=1000.0, xi_eps=1e-3,
                 euler_div=9.0, max_steps=65536, record_disk=False, disk_rmin=-1.0,
-                disk_rmax=50.0, pole_mode=POLE_MONITOR) -> Params:
+                disk_rmax=50.0, pole_mode=POLE_MONITOR, metric=METRIC_KERR, eps3=0.0) -> Params:
     return Params(step_frac, horizon_eps, r_escape, xi_eps, euler_div, disk_rmin, disk_rmax,
-                  int(max_steps), 1 if record_disk else 0, int(pole_mode), 0)
+                  int(max_steps), 1 if record_disk else 0, int(pole_mode), int(metric), float(eps3))
 
 
 _lib = None
@@ -92,6 +93,13 @@ def lib():
             "oracle_step": (ctypes.c_int, [P, d, _D, _D]),
             "oracle_conserved": (None, [d, _D, _D]),
             "oracle_disk_redshift": (d, [d, d, d, d]),
+            "oracle_metric_jp": (None, [d, d, d, d, _D]),
+            "oracle_metric_deriv_jp": (None, [d, d, d, d, _D, _D]),
+            "oracle_christoffel_jp": (None, [d, d, d, d, _D]),
+            "oracle_rhs_jp": (None, [d, d, _D, _D]),
+            "oracle_xi_jp": (d, [d, d, _D]),
+            "oracle_camera_jp": (None, [d, d, d, d, d, d, _D]),
+            "oracle_conserved_jp": (None, [d, d, _D, _D]),
             "oracle_trace": (ctypes.c_int, [P, d, _D, _I, _I, _I, _D]),
             "oracle_trace_path": (ctypes.c_int, [P, d, _D, i32, _D, _I, _I]),
             "oracle_run": (None, [P, i64, _D, _D, _I, _I, _I, _I, _D, i32]),
@@ -188,6 +196,51 @@ def conserved(a, x) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
     out = np.zeros(3)
     lib().oracle_conserved(a, _dp(x), _dp(out))
+    return out
+
+
+# --------------------------------------- deformed Kerr metric (eps3 = 0: Kerr)
+def metric_jp(a, eps3, r, th) -> np.ndarray:
+    g = np.zeros(16)
+    lib().oracle_metric_jp(a, eps3, r, th, _dp(g))
+    return g.reshape(4, 4)
+
+
+def metric_deriv_jp(a, eps3, r, th):
+    dr, dth = np.zeros(16), np.zeros(16)
+    lib().oracle_metric_deriv_jp(a, eps3, r, th, _dp(dr), _dp(dth))
+    return dr.reshape(4, 4), dth.reshape(4, 4)
+
+
+def christoffel_jp(a, eps3, r, th) -> np.ndarray:
+    G = np.zeros(64)
+    lib().oracle_christoffel_jp(a, eps3, r, th, _dp(G))
+    return G.reshape(4, 4, 4)
+
+
+def rhs_jp(a, eps3, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    f = np.zeros(8)
+    lib().oracle_rhs_jp(a, eps3, _dp(x), _dp(f))
+    return f
+
+
+def xi_jp(a, eps3, x) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().oracle_xi_jp(a, eps3, _dp(x))
+
+
+def camera_jp(a, eps3, r_obs, incl, alpha, beta) -> np.ndarray:
+    x = np.zeros(8)
+    lib().oracle_camera_jp(a, eps3, r_obs, incl, alpha, beta, _dp(x))
+    return x
+
+
+def conserved_jp(a, eps3, x) -> np.ndarray:
+    """E, L_z (constants of motion) and the Kerr expression for Q (not one)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(3)
+    lib().oracle_conserved_jp(a, eps3, _dp(x), _dp(out))
     return out
 
 

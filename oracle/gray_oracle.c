@@ -22,11 +22,20 @@
  *     construction) read as a flat, plane-parallel screen; each ray is traced
  *     backwards, k = -p.
  *
+ *   - Optionally a deformed Kerr metric (Johannsen & Psaltis 2011, one
+ *     deviation parameter eps3), the kind of non-Kerr spacetime Sec. 1 gives
+ *     as the reason to integrate the second-order equations: it has no
+ *     Carter constant. The paper gives no formula for it; see
+ *     oracle_metric_jp. Its metric derivatives are taken by the complex step
+ *     (exact to rounding, no truncation error) and the Christoffel symbols
+ *     by the same definition-based sum as for Kerr.
+ *
  * Built with -O2 -ffp-contract=off and no fast-math, so every operation is
  * a separately rounded IEEE double operation in the order written here.
  */
 #include "gray_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -123,14 +132,15 @@ static void inverse_metric(const double g[16], double gi[16])
 
 /* Christoffel symbols of the second kind from their definition,
  *   Gamma^mu_{ab} = 1/2 g^{mu nu} (d_a g_{nu b} + d_b g_{nu a} - d_nu g_{ab}),
- * stored as G[mu*16 + a*4 + b]. Only d_r and d_theta are nonzero. */
-void oracle_christoffel(double a, double r, double th, double G[64])
+ * stored as G[mu*16 + a*4 + b], given the metric and its r and theta
+ * derivatives (the metrics here depend on neither t nor phi). */
+static void christoffel_from(const double g[16], const double dgr[16], const double dgth[16], double G[64])
 {
-    double g[16], gi[16], dg[4][16];
-    oracle_metric(a, r, th, g);
+    double gi[16], dg[4][16];
     inverse_metric(g, gi);
     memset(dg, 0, sizeof dg);
-    oracle_metric_deriv(a, r, th, dg[1], dg[2]);
+    memcpy(dg[1], dgr, sizeof dg[1]);
+    memcpy(dg[2], dgth, sizeof dg[2]);
 
     for (int mu = 0; mu < 4; ++mu)
         for (int al = 0; al < 4; ++al)
@@ -143,12 +153,84 @@ void oracle_christoffel(double a, double r, double th, double G[64])
             }
 }
 
+void oracle_christoffel(double a, double r, double th, double G[64])
+{
+    double g[16], dgr[16], dgth[16];
+    oracle_metric(a, r, th, g);
+    oracle_metric_deriv(a, r, th, dgr, dgth);
+    christoffel_from(g, dgr, dgth, G);
+}
+
+/* Deformed Kerr metric of Johannsen & Psaltis (2011) with the deviation
+ * function h = eps3 r / Sigma^2 (their leading parameter epsilon_3, M = 1):
+ *   g_tt   = -(1 + h) (1 - 2 r / Sigma)
+ *   g_tphi = -(2 a r sin^2 / Sigma) (1 + h)
+ *   g_rr   = Sigma (1 + h) / (Delta + a^2 sin^2 h)
+ *   g_thth = Sigma
+ *   g_phph = sin^2 (r^2 + a^2 + 2 a^2 r sin^2 / Sigma) + h a^2 (Sigma + 2 r) sin^4 / Sigma
+ * eps3 = 0 is the Kerr metric. It is stationary and axisymmetric (E and L_z
+ * are conserved) but has no Carter constant for eps3 != 0. Evaluated in
+ * complex arithmetic so that the same expression yields the derivatives by
+ * the complex step (oracle_metric_deriv_jp). */
+static void jp_metric_c(double a, double eps3, double complex r, double complex th, double complex g[16])
+{
+    double complex s = csin(th), c = ccos(th);
+    double complex s2 = s * s;
+    double complex sig = r * r + a * a * c * c;
+    double complex del = r * r - 2.0 * r + a * a;
+    double complex h = eps3 * r / (sig * sig);
+    for (int k = 0; k < 16; ++k) g[k] = 0.0;
+    g[IX(0, 0)] = -(1.0 + h) * (1.0 - 2.0 * r / sig);
+    g[IX(0, 3)] = -(2.0 * a * r * s2 / sig) * (1.0 + h);
+    g[IX(3, 0)] = g[IX(0, 3)];
+    g[IX(1, 1)] = sig * (1.0 + h) / (del + a * a * s2 * h);
+    g[IX(2, 2)] = sig;
+    g[IX(3, 3)] = s2 * (r * r + a * a + 2.0 * a * a * r * s2 / sig) + h * a * a * (sig + 2.0 * r) * s2 * s2 / sig;
+}
+
+void oracle_metric_jp(double a, double eps3, double r, double th, double g[16])
+{
+    double complex gc[16];
+    jp_metric_c(a, eps3, r, th, gc);
+    for (int k = 0; k < 16; ++k) g[k] = creal(gc[k]);
+}
+
+/* d_r and d_theta of the deformed metric by the complex step: for f analytic
+ * and real on the real axis, f'(x) = Im f(x + i eta) / eta + O(eta^2) with no
+ * subtraction, so a tiny eta gives the derivative to rounding. */
+void oracle_metric_deriv_jp(double a, double eps3, double r, double th, double dgr[16], double dgth[16])
+{
+    const double eta = 1e-20;
+    double complex gr[16], gt[16];
+    jp_metric_c(a, eps3, r + eta * I, th, gr);
+    jp_metric_c(a, eps3, r, th + eta * I, gt);
+    for (int k = 0; k < 16; ++k) {
+        dgr[k] = cimag(gr[k]) / eta;
+        dgth[k] = cimag(gt[k]) / eta;
+    }
+}
+
+void oracle_christoffel_jp(double a, double eps3, double r, double th, double G[64])
+{
+    double g[16], dgr[16], dgth[16];
+    oracle_metric_jp(a, eps3, r, th, g);
+    oracle_metric_deriv_jp(a, eps3, r, th, dgr, dgth);
+    christoffel_from(g, dgr, dgth, G);
+}
+
+/* Covariant metric of the spacetime the parameters select. */
+static void metric_of(const oracle_params *p, double a, double r, double th, double g[16])
+{
+    if (p->metric == ORACLE_METRIC_JP)
+        oracle_metric_jp(a, p->eps3, r, th, g);
+    else
+        oracle_metric(a, r, th, g);
+}
+
 /* Right-hand side of the geodesic equation for the 8-vector state:
  * dx^mu/dl = k^mu, dk^mu/dl = -Gamma^mu_{ab} k^a k^b. */
-void oracle_rhs(double a, const double x[8], double f[8])
+static void rhs_from(const double G[64], const double x[8], double f[8])
 {
-    double G[64];
-    oracle_christoffel(a, x[1], x[2], G);
     for (int mu = 0; mu < 4; ++mu) f[mu] = x[4 + mu];
     for (int mu = 0; mu < 4; ++mu) {
         double acc = 0.0;
@@ -157,6 +239,28 @@ void oracle_rhs(double a, const double x[8], double f[8])
                 acc += G[mu * 16 + al * 4 + be] * x[4 + al] * x[4 + be];
         f[4 + mu] = -acc;
     }
+}
+
+void oracle_rhs(double a, const double x[8], double f[8])
+{
+    double G[64];
+    oracle_christoffel(a, x[1], x[2], G);
+    rhs_from(G, x, f);
+}
+
+void oracle_rhs_jp(double a, double eps3, const double x[8], double f[8])
+{
+    double G[64];
+    oracle_christoffel_jp(a, eps3, x[1], x[2], G);
+    rhs_from(G, x, f);
+}
+
+static void rhs_of(const oracle_params *p, double a, const double x[8], double f[8])
+{
+    if (p->metric == ORACLE_METRIC_JP)
+        oracle_rhs_jp(a, p->eps3, x, f);
+    else
+        oracle_rhs(a, x, f);
 }
 
 /* Initial state of one ray. The observer sits at distance D = r_obs in the
@@ -169,7 +273,8 @@ void oracle_rhs(double a, const double x[8], double f[8])
  * integrated is k = -p (the ray is traced back towards the hole).
  * A ray exactly on the spin axis (incl = 0, alpha = beta = 0) has undefined
  * theta and phi directions; it is given p^theta = p^phi = 0 there. */
-void oracle_camera(double a, double r_obs, double incl, double alpha, double beta, double x[8])
+static void camera_in(int metric, double eps3, double a, double r_obs, double incl, double alpha, double beta,
+                      double x[8])
 {
     double D = r_obs;
     double si = sin(incl), ci = cos(incl);
@@ -194,7 +299,10 @@ void oracle_camera(double a, double r_obs, double incl, double alpha, double bet
     }
 
     double g[16];
-    oracle_metric(a, r0, th0, g);
+    if (metric == ORACLE_METRIC_JP)
+        oracle_metric_jp(a, eps3, r0, th0, g);
+    else
+        oracle_metric(a, r0, th0, g);
     double S = g[IX(1, 1)] * pr * pr + g[IX(2, 2)] * pth * pth + g[IX(3, 3)] * pph * pph;
     double B = g[IX(0, 3)] * pph;
     /* g_tt (p^t)^2 + 2 B p^t + S = 0, root with p^t > 0 (g_tt < 0 far out). */
@@ -208,6 +316,17 @@ void oracle_camera(double a, double r_obs, double incl, double alpha, double bet
     x[5] = -pr;
     x[6] = -pth;
     x[7] = -pph;
+}
+
+void oracle_camera(double a, double r_obs, double incl, double alpha, double beta, double x[8])
+{
+    camera_in(ORACLE_METRIC_KERR, 0.0, a, r_obs, incl, alpha, beta, x);
+}
+
+/* The same screen in the deformed metric (p^t from its null condition). */
+void oracle_camera_jp(double a, double eps3, double r_obs, double incl, double alpha, double beta, double x[8])
+{
+    camera_in(ORACLE_METRIC_JP, eps3, a, r_obs, incl, alpha, beta, x);
 }
 
 /* Regular cell-centred grid of rays; pixel id = iy * nx + ix. */
@@ -235,14 +354,26 @@ double oracle_step_size(double rbh, double step_frac, const double x[8])
 }
 
 /* Null-condition monitor xi of Sec. 2 eq. (4); -1 on an exact null ray. */
-double oracle_xi(double a, const double x[8])
+static double xi_with(const double g[16], const double x[8])
 {
-    double g[16];
-    oracle_metric(a, x[1], x[2], g);
     double kt = x[4], kr = x[5], kth = x[6], kph = x[7];
     double num = g[IX(1, 1)] * kr * kr + g[IX(3, 3)] * kph * kph + g[IX(2, 2)] * kth * kth +
                  2.0 * g[IX(0, 3)] * kt * kph;
     return num / (g[IX(0, 0)] * kt * kt);
+}
+
+double oracle_xi(double a, const double x[8])
+{
+    double g[16];
+    oracle_metric(a, x[1], x[2], g);
+    return xi_with(g, x);
+}
+
+double oracle_xi_jp(double a, double eps3, const double x[8])
+{
+    double g[16];
+    oracle_metric_jp(a, eps3, x[1], x[2], g);
+    return xi_with(g, x);
 }
 
 /* Remap of Sec. 2 eq. (3), keeping theta in [0, pi]. Returns 1 if applied. */
@@ -277,13 +408,13 @@ int oracle_step(const oracle_params *p, double a, double x[8], double *h_used)
     if (!(h > 0.0 && h < INFINITY)) return -1;
 
     double k1[8], k2[8], k3[8], k4[8], y[8], xn[8];
-    oracle_rhs(a, x, k1);
+    rhs_of(p, a, x, k1);
     for (int i = 0; i < 8; ++i) y[i] = x[i] + 0.5 * h * k1[i];
-    oracle_rhs(a, y, k2);
+    rhs_of(p, a, y, k2);
     for (int i = 0; i < 8; ++i) y[i] = x[i] + 0.5 * h * k2[i];
-    oracle_rhs(a, y, k3);
+    rhs_of(p, a, y, k3);
     for (int i = 0; i < 8; ++i) y[i] = x[i] + h * k3[i];
-    oracle_rhs(a, y, k4);
+    rhs_of(p, a, y, k4);
     for (int i = 0; i < 8; ++i)
         xn[i] = x[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
 
@@ -291,7 +422,9 @@ int oracle_step(const oracle_params *p, double a, double x[8], double *h_used)
     if (p->pole_mode == 0) {
         /* production scheme: re-integrate with Euler at h / euler_div when
          * the step violates the null condition, eq. (4) */
-        double xi = oracle_xi(a, xn);
+        double gn[16];
+        metric_of(p, a, xn[1], xn[2], gn);
+        double xi = xi_with(gn, xn);
         if (fabs(xi + 1.0) > p->xi_eps) {
             double he = h / p->euler_div;
             for (int i = 0; i < 8; ++i) xn[i] = x[i] + he * k1[i];
@@ -313,10 +446,8 @@ int oracle_step(const oracle_params *p, double a, double x[8], double *h_used)
 /* Conserved quantities of the photon's physical momentum p = -k:
  * energy E = -p_t, axial angular momentum L = p_phi and Carter's constant
  * Q = p_theta^2 + cos^2 theta (L^2 / sin^2 theta - a^2 E^2) (Sec. 1). */
-void oracle_conserved(double a, const double x[8], double out[3])
+static void conserved_with(double a, const double g[16], const double x[8], double out[3])
 {
-    double g[16];
-    oracle_metric(a, x[1], x[2], g);
     double p[4] = {-x[4], -x[5], -x[6], -x[7]};
     double pl[4];
     for (int mu = 0; mu < 4; ++mu) {
@@ -328,6 +459,23 @@ void oracle_conserved(double a, const double x[8], double out[3])
     out[0] = E;
     out[1] = L;
     out[2] = pl[2] * pl[2] + c * c * (L * L / (s * s) - a * a * E * E);
+}
+
+void oracle_conserved(double a, const double x[8], double out[3])
+{
+    double g[16];
+    oracle_metric(a, x[1], x[2], g);
+    conserved_with(a, g, x, out);
+}
+
+/* E and L_z in the deformed metric (still constants of motion); the third
+ * entry is the Kerr expression for Q with this metric's p_theta, which is not
+ * conserved when eps3 != 0. */
+void oracle_conserved_jp(double a, double eps3, const double x[8], double out[3])
+{
+    double g[16];
+    oracle_metric_jp(a, eps3, x[1], x[2], g);
+    conserved_with(a, g, x, out);
 }
 
 /* Redshift factor g = 1 / (u^t (1 - Omega L/E)) of light emitted at radius rc

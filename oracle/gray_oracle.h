@@ -21,6 +21,8 @@
 extern "C" {
 #endif
 
+enum { ORACLE_METRIC_KERR = 0, ORACLE_METRIC_JP = 1 };
+
 enum { ORACLE_RUNNING = 0, ORACLE_CAPTURED = 1, ORACLE_ESCAPED = 2,
        ORACLE_UNFINISHED = 3, ORACLE_NONFINITE = 4 };
 
@@ -39,7 +41,10 @@ typedef struct {
                            1 earlier scheme: one Euler step of the same h whenever
                              the RK4 step crosses a pole;
                            2 none: RK4 and the remap of eq. (3) only             */
-    int32_t pad;
+    int32_t metric;     /* ORACLE_METRIC_KERR, or ORACLE_METRIC_JP: the deformed
+                           Kerr metric of oracle_metric_jp with deviation eps3
+                           (camera states for it come from oracle_camera_jp)   */
+    double eps3;
 } oracle_params;
 
 typedef struct {
@@ -56,6 +61,17 @@ void oracle_metric(double a, double r, double th, double g[16]);
 void oracle_metric_deriv(double a, double r, double th, double dgr[16], double dgth[16]);
 void oracle_christoffel(double a, double r, double th, double G[64]);
 void oracle_rhs(double a, const double x[8], double f[8]);
+
+/* Deformed Kerr metric (Johannsen & Psaltis 2011, deviation eps3; eps3 = 0 is
+ * Kerr): metric, complex-step derivatives, Christoffel symbols, RHS, null
+ * monitor, camera and constants (E, L_z; Q in its Kerr form). */
+void oracle_metric_jp(double a, double eps3, double r, double th, double g[16]);
+void oracle_metric_deriv_jp(double a, double eps3, double r, double th, double dgr[16], double dgth[16]);
+void oracle_christoffel_jp(double a, double eps3, double r, double th, double G[64]);
+void oracle_rhs_jp(double a, double eps3, const double x[8], double f[8]);
+double oracle_xi_jp(double a, double eps3, const double x[8]);
+void oracle_camera_jp(double a, double eps3, double r_obs, double incl, double alpha, double beta, double x[8]);
+void oracle_conserved_jp(double a, double eps3, const double x[8], double out[3]);
 
 /* Image plane. */
 void oracle_camera(double a, double r_obs, double incl, double alpha, double beta, double x[8]);
