@@ -29,8 +29,14 @@ sys.path.insert(0, ROOT)
 # path: RK4 + step size + null-condition check), weights add/mul 1, fma 2,
 # div/sqrt/sin/cos 1; produced by csrc/flopcount.cpp and checked by the tests.
 F_STEP = {"fp64": 572, "fp32c": 572}
-# MI355X published vector peaks, TFLOP/s (256 CUs at 2.4 GHz).
-PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
+# MI355X published vector peaks, TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# x 2.4 GHz). FP32 reaches 157.3 only with packed (two-per-lane) FP32
+# instructions, which this library does not use; its float code issues at the
+# FP64 rate, so both precisions are held to 78.6.
+PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 78.6}
+# Rays closer than this to the critical curve (M, on the ray's own constants of
+# motion) may legitimately differ in outcome between two correct integrators.
+BAND = 1e-3
 
 
 def measured_traffic(prec: str):
@@ -63,6 +69,8 @@ def parse():
                     help="oracle traces every k-th row and column of the grid")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 4096x4096 recorder workload")
+    ap.add_argument("--no-deformed", action="store_true", help="skip the deformed-metric timing")
     ap.add_argument("--no-ring", action="store_true", help="skip the photon-ring study")
     ap.add_argument("--no-pole", action="store_true", help="skip the pole-treatment ablation")
     ap.add_argument("--no-floor", action="store_true",
@@ -177,6 +185,7 @@ def cpu_baseline(cam, params, every: int):
     res = oracle.run(p, cam.a, X0, nthreads=threads)
     dt = time.perf_counter() - t0
     nsteps = int(res.steps.sum())
+    cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
     # one thread on the 64 x 64 Schwarzschild grid (full grid)
     c1 = W.C1
     X1 = oracle.camera_grid(c1.a, c1.r_obs, c1.incl, c1.nx, c1.ny, c1.alpha_lo, c1.alpha_hi,
@@ -192,13 +201,74 @@ def cpu_baseline(cam, params, every: int):
                 break
     except OSError:
         pass
-    return {"value": dt * 1e9 / nsteps, "unit": "ns/photon/step", "cores": threads,
-            "kind": "oracle",
-            "sample": f"every {every} row(s) and column(s) of the 512x512 grid "
-                      f"({len(ids)} rays, {nsteps} photon-steps, {dt:.2f} s wall)",
-            "per_core_ns_per_photon_step": dt * 1e9 / nsteps * threads,
-            "single_thread_64x64_schwarzschild_ns_per_photon_step": dt1 * 1e9 / int(r1.steps.sum()),
-            "nproc": os.cpu_count(), "cpu_model": model}
+    summary = {"value": dt * 1e9 / nsteps, "unit": "ns/photon/step", "cores": threads,
+               "kind": "oracle",
+               "sample": f"every {every} row(s) and column(s) of the 512x512 grid "
+                         f"({len(ids)} rays, {nsteps} photon-steps, {dt:.2f} s wall)",
+               "per_core_ns_per_photon_step": dt * 1e9 / nsteps * threads,
+               "single_thread_64x64_schwarzschild_ns_per_photon_step": dt1 * 1e9 / int(r1.steps.sum()),
+               "nproc": os.cpu_count(), "cpu_model": model}
+    ref = {"ids": ids, "status": res.status, "steps": res.steps, "x": res.x, "euler": res.n_euler,
+           "band": band_distance(cam, cons0[:, 0], cons0[:, 1], cons0[:, 2])}
+    return summary, ref
+
+
+def oracle_sample(cam, params, ids):
+    """FP64 oracle traces of the listed pixels of `cam` (for C3's error check)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import numpy as np
+    import oracle
+
+    if not os.path.exists(oracle._LIB):
+        oracle.build()
+    iy, ix = ids // cam.nx, ids % cam.nx
+    al = cam.alpha_lo + (cam.alpha_hi - cam.alpha_lo) * ((ix + 0.5) / cam.nx)
+    be = cam.beta_lo + (cam.beta_hi - cam.beta_lo) * ((iy + 0.5) / cam.ny)
+    X0 = np.array([oracle.camera(cam.a, cam.r_obs, cam.incl, x, y) for x, y in zip(al, be)])
+    p = oracle.make_params(step_frac=params.step_frac, horizon_eps=params.horizon_eps,
+                           r_escape=params.r_escape, xi_eps=params.xi_eps,
+                           euler_div=params.euler_div, max_steps=params.max_steps,
+                           record_disk=params.record_disk, disk_rmin=params.disk_rmin,
+                           disk_rmax=params.disk_rmax)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    res = oracle.run(p, cam.a, X0, nthreads=threads, want_disk=params.record_disk)
+    cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
+    return {"ids": ids, "status": res.status, "steps": res.steps, "x": res.x, "euler": res.n_euler,
+            "band": band_distance(cam, cons0[:, 0], cons0[:, 1], cons0[:, 2]), "disk": res.disk}
+
+
+def error_vs_oracle(np, g: dict, ref: dict, gathered: bool = False) -> dict:
+    """Final states of one GPU run against the FP64 oracle's on the same rays.
+
+    State error per ray: max over components of |x_gpu - x_ora| / (|x_ora| + f)
+    with f = 1 for t, r, theta, phi, k^t, k^r and 1/r for k^theta, k^phi,
+    over rays whose outcome and step count agree, outside the 1e-3 M band.
+    Also the fraction of those rays whose step counts differ, the outcome
+    mismatches outside the band, and the rays the FP32C parity rule leaves out
+    of state comparison (within 1e-2 M of the critical curve, or more than 10%
+    Euler steps in the oracle)."""
+    ids = np.arange(len(ref["ids"])) if gathered else ref["ids"]
+    st, sp, x = g["status"][ids], g["steps"][ids], g["x"][ids]
+    far = ref["band"] > BAND
+    same = (st == ref["status"]) & (sp == ref["steps"])
+    r = np.abs(ref["x"][:, 1])
+    floor = np.stack([np.ones_like(r)] * 6 + [1.0 / r, 1.0 / r], axis=1)
+    err = (np.abs(x - ref["x"]) / (np.abs(ref["x"]) + floor)).max(axis=1)
+    sel = same & far
+    e = err[sel]
+    locked = ref["euler"] > 0.1 * ref["steps"]
+    excluded = (ref["band"] <= 1e-2) | locked
+    mism = (~same) & far
+    return {"rays": int(len(ids)), "outside_band": int(far.sum()),
+            "outcome_mismatch_outside_band": int(((st != ref["status"]) & far).sum()),
+            "step_mismatch_fraction_outside_band": float(mism.sum() / max(1, far.sum())),
+            "step_mismatch_outside_1e-2_band_not_locked": int((mism & ~excluded).sum()),
+            "state_err": {"p50": float(np.percentile(e, 50)), "p99": float(np.percentile(e, 99)),
+                          "max": float(e.max())} if e.size else None,
+            "state_err_outside_fp32c_exclusions_max": float(err[sel & ~excluded].max()) if (sel & ~excluded).any() else None,
+            "fp32c_rule_excluded_fraction": float(excluded.mean()),
+            "fp32c_rule_excluded": {"within_1e-2_band": int((ref["band"] <= 1e-2).sum()),
+                                    "euler_locked": int(locked.sum())}}
 
 
 def projection_nsweep(G, W, torch, np) -> dict:
@@ -297,7 +367,7 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int, floor: boo
         b.integrate()
         if ev1 is not None:
             ev1.record()
-        return b.classify(xf=False, cons=True, counts=True)
+        return b.classify(xf=True, cons=True, counts=True)
 
     for _ in range(warmup):
         one_pass()
@@ -319,17 +389,45 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int, floor: boo
     status = b.status[: b.n].cpu().numpy()
     cons = res.cons.view(9, b.stride)[:, : b.n].cpu().numpy()
     euler = b.counters.view(3, b.stride)[0, : b.n].cpu().numpy()
-    drift = {}
-    for name, sel in (("escaped", status == G.ESCAPED), ("captured", status == G.CAPTURED),
-                      ("no_fallback", euler == 0)):
-        d = cons[6:9, sel]
-        drift[name] = {q: np.percentile(d, pq, axis=1).tolist()
-                       for q, pq in (("p50", 50), ("p99", 99), ("max", 100))} if d.size else {}
+    band = band_distance(cam, cons[0], cons[1], cons[2])
+    drift = drift_groups(G, np, status, cons, euler, band)
     tail = longest_alone(G, W, torch, np, b, params) if floor else None
+    xf = res.xf.view(8, b.stride)[:, : b.n].cpu().numpy().T if res.xf is not None else None
     return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
             "total_steps": total_steps, "status": np.bincount(status, minlength=5).tolist(),
             "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n,
-            "lane_efficiency": lane_eff, "tail": tail}
+            "lane_efficiency": lane_eff, "tail": tail,
+            "host": {"status": status, "steps": b.steps[: b.n].cpu().numpy(), "x": xf,
+                     "euler": euler, "band": band}}
+
+
+def band_distance(cam, E0, L0, Q0):
+    """Distance (M) of each ray's asymptotic image-plane point, from its own
+    constants of motion at the camera, to the Kerr critical curve."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import analytic
+    return analytic.CriticalBand(cam.a, cam.incl).distance(E0, L0, Q0)
+
+
+def drift_groups(G, np, status, cons, euler, band) -> dict:
+    """Drift of E, L_z and Q (rows 6..8 of gray_classify's cons) per group of
+    rays: outcome (escaped, captured) x position (outside or inside the 1e-3 M
+    band around the critical curve) x Euler fallbacks (none, some). For each
+    group: ray count, p50 / p99 / max of each drift, and how many rays exceed
+    1e-5 in each quantity."""
+    out = {}
+    for oname, osel in (("escaped", status == G.ESCAPED), ("captured", status == G.CAPTURED)):
+        for bname, bsel in (("outside_band", band > BAND), ("in_band", band <= BAND)):
+            for ename, esel in (("no_euler", euler == 0), ("euler", euler > 0)):
+                sel = osel & bsel & esel
+                d = cons[6:9, sel]
+                g = {"rays": int(sel.sum())}
+                if d.size:
+                    g.update({q: np.percentile(d, pq, axis=1).tolist()
+                              for q, pq in (("p50", 50), ("p99", 99), ("max", 100))})
+                    g["above_1e-5"] = (d > 1e-5).sum(axis=1).tolist()
+                out[f"{oname}/{bname}/{ename}"] = g
+    return out
 
 
 def longest_alone(G, W, torch, np, b, params, reps: int = 3) -> dict:
@@ -390,15 +488,11 @@ def main():
     print("bench: timing the 512x512 workload", file=sys.stderr, flush=True)
     head = measure(G, W, torch, np, cam, args.precision, args.steps, args.warmup, not args.no_floor)
     other_prec = "fp32c" if args.precision == "fp64" else "fp64"
-    other = measure(G, W, torch, np, cam, other_prec, args.steps, args.warmup, False)
+    other = measure(G, W, torch, np, cam, other_prec, args.steps, args.warmup, not args.no_floor)
     t64 = head["integrate_ms"] if args.precision == "fp64" else other["integrate_ms"]
     t32 = other["integrate_ms"] if args.precision == "fp64" else head["integrate_ms"]
 
     total_steps = head["total_steps"]
-    achieved = F_STEP[args.precision] * total_steps / (head["integrate_ms"] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    kernel = ("k_integrate<GRAY_FP64, kPoleMonitor>" if args.precision == "fp64"
-              else "k_integrate<GRAY_FP32C, kPoleMonitor>")
     out = {
         "metric": "ns/photon/step",
         "value": head["ms_per_step"] * 1e6 / total_steps,
@@ -423,22 +517,27 @@ def main():
         "euler_fallback_steps": head["euler_steps"],
         "lane_efficiency": head["lane_efficiency"],
         # the launch's floor: its longest photon alone on the GPU
-        "longest_photon": (dict(head["tail"], launch_ms=head["integrate_ms"],
-                                floor_fraction=head["tail"]["alone_ms"] / head["integrate_ms"])
-                           if head["tail"] else None),
+        "longest_photon": floor_block(head),
         "drift_ELQ": head["drift"],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(args.precision),
-                     "traffic_unit": "bytes per launch", "kernel": kernel,
-                     "flops_per_photon_step": F_STEP[args.precision]},
+        "roofline": roofline(args.precision, head, measured_traffic(args.precision)),
         other_prec: {"ns_per_photon_step": other["ms_per_step"] * 1e6 / other["total_steps"],
                      "integrate_ms": other["integrate_ms"],
                      "photon_steps_per_pass": other["total_steps"],
                      "fp64_step_fraction": other["fp64_steps"] / other["total_steps"],
                      "lane_efficiency": other["lane_efficiency"],
-                     "status_counts": other["status"], "drift_ELQ": other["drift"]},
+                     "status_counts": other["status"], "drift_ELQ": other["drift"],
+                     "longest_photon": floor_block(other),
+                     "roofline": roofline(other_prec, other, measured_traffic(other_prec))},
         "fp32c_speedup_vs_fp64": t64 / t32,
     }
+    if args.precision == "fp32c":
+        out["fp64_step_fraction"] = head["fp64_steps"] / total_steps
+    if not args.no_c3:
+        print("bench: 4096x4096 recorder workload", file=sys.stderr, flush=True)
+        out["c3"] = c3_block(G, W, torch, np, with_oracle=not args.no_cpu_baseline)
+    if not args.no_deformed:
+        print("bench: deformed metric", file=sys.stderr, flush=True)
+        out["deformed"] = deformed_block(G, W, torch, np)
     if not args.no_sweep:
         print("bench: 256-camera sweep", file=sys.stderr, flush=True)
         out["sweep"] = sweep(G, W, torch, np)
@@ -456,9 +555,130 @@ def main():
         out["serving"] = serving(args)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cam, head["params"], args.cpu_sample)
+        out["cpu_baseline"], ref = cpu_baseline(cam, head["params"], args.cpu_sample)
+        # the same oracle traces, against both precisions' final states
+        out["error_vs_oracle"] = {args.precision: error_vs_oracle(np, head["host"], ref),
+                                  other_prec: error_vs_oracle(np, other["host"], ref)}
     print(json.dumps(out), flush=True)
     return 0
+
+
+def roofline(prec: str, m: dict, traffic) -> dict:
+    """The integrate kernel against the VALU peak: algorithmic flops per
+    accepted photon-step times the launch's photon-steps over its HIP-event
+    time."""
+    achieved = F_STEP[prec] * m["total_steps"] / (m["integrate_ms"] * 1e-3) / 1e12
+    kernel = "k_integrate<GRAY_FP64, kPoleMonitor>" if prec == "fp64" else "k_integrate<GRAY_FP32C, kPoleMonitor>"
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic, "traffic_unit": "bytes per launch",
+            "kernel": kernel, "flops_per_photon_step": F_STEP[prec]}
+
+
+def floor_block(m: dict):
+    if not m["tail"]:
+        return None
+    return dict(m["tail"], launch_ms=m["integrate_ms"], floor_fraction=m["tail"]["alone_ms"] / m["integrate_ms"])
+
+
+def deformed_block(G, W, torch, np, reps: int = 3) -> dict:
+    """The metric-generic path: a = 0.6, i = 50 deg, 512 x 512 over +-8 M in
+    the deformed Kerr metric (deform = 1.5), and the same camera through the
+    generic path at deform = 0 and through the Kerr fast path, FP64:
+    integrate time, ns per photon-step, and drift of E and L_z (constants of
+    motion of the deformed metric) and of the Kerr-form Q (not one)."""
+    out = {"workload": "deformed_kerr_a0.6_i50_512x512_r1000"}
+    for name, metric, deform in (("deformed_1.5", G.GRAY_METRIC_DEFORMED, 1.5),
+                                 ("generic_0", G.GRAY_METRIC_DEFORMED, 0.0),
+                                 ("kerr_fast_path", G.GRAY_METRIC_KERR, 0.0)):
+        cam = W.Camera(0.6, 1000.0, W.deg(50.0), 512, 512, -8.0, 8.0, -8.0, 8.0, metric=metric, deform=deform)
+        b = G.Batch([cam], W.Params(), counters=True, mark=True)
+        ms = []
+        for rep in range(reps):
+            b.camera_init()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.integrate()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        res = b.classify(xf=False, cons=True, counts=True)
+        torch.cuda.synchronize()
+        n = b.n
+        steps = int(b.steps[:n].to(torch.int64).sum().item())
+        status = b.status[:n].cpu().numpy()
+        cons = res.cons.view(9, b.stride)[:, :n].cpu().numpy()
+        euler = b.counters.view(3, b.stride)[0, :n].cpu().numpy()
+        clean = (status == G.ESCAPED) & (euler == 0)
+        out[name] = {"integrate_ms": min(ms), "photon_steps": steps, "ns_per_photon_step": min(ms) * 1e6 / steps,
+                     "status_counts": np.bincount(status, minlength=5).tolist(),
+                     "escaped_no_euler_drift_max_E_L_Q": cons[6:9, clean].max(axis=1).tolist() if clean.any() else None}
+        del b, res
+        torch.cuda.empty_cache()
+    out["generic_over_fast_path_time"] = out["generic_0"]["integrate_ms"] / out["kerr_fast_path"]["integrate_ms"]
+    return out
+
+
+def c3_block(G, W, torch, np, with_oracle: bool, reps: int = 3) -> dict:
+    """The 4096 x 4096 face-on-ish workload (a = 0.9375, i = 17 deg, window
+    +-12 M, equatorial-crossing recorder over [r_ISCO, 50 M]) in FP32C (the
+    precision it is specified in) and FP64: integrate time (best of `reps`,
+    HIP events), ns per photon-step, the FP64-step fraction, drift groups, the
+    fraction of rays that hit the recorder window, the roofline, and the
+    error against the FP64 oracle on every 64th row and column."""
+    cam = W.C3
+    out = {"workload": "kerr_a0.9375_i17_4096x4096_r1000_disk", "photons": cam.n}
+    ids = W.subsample_ids(cam, 64)
+    ref = oracle_sample(cam, W.C3_PARAMS, ids) if with_oracle else None
+    t = {}
+    for prec in ("fp32c", "fp64"):
+        params = W.Params(record_disk=True, disk_rmin=-1.0, disk_rmax=50.0, precision=prec)
+        b = G.Batch([cam], params, counters=True, mark=True)
+        ms = []
+        for rep in range(reps):
+            b.camera_init()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.integrate()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        res = b.classify(xf=True, cons=True, counts=True)
+        torch.cuda.synchronize()
+        n = b.n
+        steps = int(b.steps[:n].to(torch.int64).sum().item())
+        ctr = b.counters.view(3, b.stride)[:, :n].to(torch.int64).sum(dim=1).tolist()
+        status = b.status[:n].cpu().numpy()
+        cons = res.cons.view(9, b.stride)[:, :n].cpu().numpy()
+        euler = b.counters.view(3, b.stride)[0, :n].cpu().numpy()
+        band = band_distance(cam, cons[0], cons[1], cons[2])
+        disk_r = b.disk.view(3, b.stride)[0, :n]
+        m = {"integrate_ms": min(ms), "total_steps": steps}
+        blk = {"integrate_ms": min(ms), "integrate_ms_all": ms, "photon_steps": steps,
+               "ns_per_photon_step": min(ms) * 1e6 / steps, "photon_steps_per_s": steps / (min(ms) * 1e-3),
+               "fp64_step_fraction": ctr[2] / steps, "euler_steps": ctr[0],
+               "status_counts": np.bincount(status, minlength=5).tolist(),
+               "disk_hit_fraction": float((disk_r > 0).float().mean().item()),
+               "drift_ELQ": drift_groups(G, np, status, cons, euler, band),
+               "roofline": roofline(prec, m, None)}
+        if ref is not None:
+            # the sampled rays only, gathered on the device
+            idx = torch.as_tensor(ids, dtype=torch.int64, device=b.x.device)
+            g = {"status": b.status[idx].cpu().numpy(), "steps": b.steps[idx].cpu().numpy(),
+                 "x": res.xf.view(8, b.stride)[:, idx].cpu().numpy().T}
+            blk["error_vs_oracle"] = error_vs_oracle(np, g, ref, gathered=True)
+            dg = b.disk.view(3, b.stride)[:, idx].cpu().numpy().T
+            agree = (g["status"] == ref["status"]) & (g["steps"] == ref["steps"])
+            same = agree & (ref["disk"][:, 0] > 0) & (ref["band"] > 1e-2)
+            de = np.abs(dg[same] - ref["disk"][same]) / (np.abs(ref["disk"][same]) + 1.0)
+            blk["error_vs_oracle"]["disk_err_max"] = float(de.max()) if de.size else None
+            blk["error_vs_oracle"]["disk_hit_mismatch"] = int(
+                ((dg[:, 0] > 0) != (ref["disk"][:, 0] > 0))[agree].sum())
+        out[prec] = blk
+        t[prec] = min(ms)
+        del b, res
+        torch.cuda.empty_cache()
+    out["fp32c_speedup_vs_fp64"] = t["fp64"] / t["fp32c"]
+    return out
 
 
 if __name__ == "__main__":

@@ -115,6 +115,33 @@ typedef enum {
                               in the photon-ring study of Sec. 4                 */
 } gray_camera_kind;
 
+/* gray_camera.metric: the spacetime the camera looks at */
+typedef enum {
+    GRAY_METRIC_KERR = 0,     /* Kerr, spin a (deform must be 0)                    */
+    GRAY_METRIC_DEFORMED = 1  /* Kerr deformed by the Johannsen-Psaltis deviation
+                                 function h = deform * r / Sigma^2 (deform = their
+                                 epsilon_3; deform = 0 is Kerr), a non-Kerr
+                                 spacetime without a Carter constant, the case
+                                 Sec. 1 gives for integrating the second-order
+                                 equations:
+                                   g_tt   = -(1 + h)(1 - 2 r / Sigma)
+                                   g_tphi = -(2 a r sin^2 / Sigma)(1 + h)
+                                   g_rr   = Sigma (1 + h) / (Delta + a^2 sin^2 h)
+                                   g_thth = Sigma
+                                   g_phph = sin^2 (r^2 + a^2 + 2 a^2 r sin^2 / Sigma)
+                                            + h a^2 (Sigma + 2 r) sin^4 / Sigma
+                                 Requires deform >= 0 (or a = 0 and deform > -8),
+                                 where the metric is regular outside the Kerr
+                                 horizon r_bh, which the step-size rule and the
+                                 capture radius keep using. Served in GRAY_FP64
+                                 with GRAY_POLE_MONITOR and without
+                                 GRAY_RECORD_DISK (GRAY_EUNSUPPORTED otherwise);
+                                 all cameras of a call share one metric kind.
+                                 gray_classify reports E and L_z in this metric
+                                 (constants of motion) and Carter's Q in its Kerr
+                                 form, which drifts when deform != 0.          */
+} gray_metric;
+
 /* One camera: a Kerr hole of spin a seen from distance r_obs at inclination
  * incl (radians from the spin axis, azimuth 0), with a regular nx * ny grid
  * on a flat image plane perpendicular to the line of sight (Sec. 2 and Sec. 3
@@ -138,7 +165,8 @@ typedef struct {
     double alpha_lo, alpha_hi, beta_lo, beta_hi;
     int64_t first;
     int32_t kind;      /* gray_camera_kind */
-    int32_t reserved;  /* 0 */
+    int32_t metric;    /* gray_metric      */
+    double deform;     /* deviation of GRAY_METRIC_DEFORMED; 0 for Kerr */
 } gray_camera;
 
 /* Treatment of steps near the polar axis, where Boyer-Lindquist coordinates

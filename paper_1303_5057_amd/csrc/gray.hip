@@ -78,15 +78,15 @@ static_assert(sizeof(WsHeader) <= kWsHeader, "header fits its reserved space");
 
 // Per-camera constants the integrator needs, kept in the workspace.
 struct DevCam {
-    double a, a2, rbh, rcap, rmark, disk_rmin, disk_rmax, pad;
+    double a, a2, rbh, rcap, rmark, disk_rmin, disk_rmax, eps3;
 };
 static_assert(sizeof(DevCam) == 64, "DevCam is one 64-byte record");
 
 // Camera geometry passed by value to the init and classify kernels.
 struct CamArg {
-    double a, r_obs, incl, alo, ahi, blo, bhi;
+    double a, r_obs, incl, alo, ahi, blo, bhi, eps3;
     int64_t first;
-    int32_t nx, ny, index, kind;
+    int32_t nx, ny, index, kind, metric, pad;
 };
 struct CamChunk {
     CamArg c[kCamChunk];
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_camera_init(InitArgs A)
     double alpha, beta;
     pixel_of(c, i, alpha, beta);
     State<double> x;
-    camera_state(c.a, c.r_obs, c.incl, alpha, beta, x);
+    camera_state(c.a, c.r_obs, c.incl, alpha, beta, x, c.eps3, c.metric == GRAY_METRIC_DEFORMED);
     const int64_t S = A.stride;
     if (A.precision == GRAY_FP64) {
         double *X = (double *)A.x;
@@ -513,6 +513,7 @@ template <>
 struct Lane<GRAY_FP32C> {
     State<float> hi, lo;
     float s, c;
+    bool locked;   // the state fails the float guard of the null monitor
     __device__ __forceinline__ void load(const void *hp, const void *lp, int64_t S, int64_t id)
     {
         Column<const float> H((const float *)hp, S, id), L((const float *)lp, S, id);
@@ -576,10 +577,14 @@ __device__ __forceinline__ bool finite_state(const State<double> &x)
 // so every wave exits. PM is the treatment of the polar axis (FP64 only;
 // the production monitor unless a caller asks for one of the paper's
 // earlier treatments), a template parameter so that the production kernel
-// carries no code for the others.
-template <int P, int PM = kPoleMonitor>
+// carries no code for the others; MET selects the spacetime (Kerr, or the
+// deformed metric through the metric-generic right-hand side).
+template <int P, int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR>
 __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
+    static_assert(MET == GRAY_METRIC_KERR || (P == GRAY_FP64 && PM == kPoleMonitor),
+                  "the deformed metric is integrated in FP64 with the production pole treatment");
+    using Space = typename std::conditional<MET == GRAY_METRIC_DEFORMED, DeformedSpin, Spin<double>>::type;
     const unsigned lane = threadIdx.x & (kWave - 1);
     const bool record_disk = (A.flags & GRAY_RECORD_DISK) != 0;
     const bool record_mark = A.mark != nullptr;
@@ -589,10 +594,14 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     bool active = false;
     int64_t id = 0;
     Lane<P> L;
-    StepConst<double> K;
+    StepConst<double, Space> K;
     StepConst<float> Kf;
     double rcap = 0.0, resc = 0.0;
-    float r64 = 0.0f;
+    // FP32C: float thresholds of the photon (FP64 zone, capture and mark
+    // radii, the mark band) and of the call (pole, turning point, escape)
+    float r64 = 0.0f, rcap_f = 0.0f, rmark_f = 0.0f, rband_f = 0.0f;
+    const float pole_f = (float)A.fp64_pole, turn_f = (float)A.fp64_turn;
+    const float resc_f = (float)(A.r_escape * (1.0 - 1e-6));
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
 
@@ -660,7 +669,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                     if (id >= 0 && glob(PA.status)[id] == GRAY_RUNNING) {
                         L.load(PA.x, PA.lo, S, id);
                         const DevCam cm = PA.cams[glob(PA.cam)[id]];
-                        K.B = make_spin(cm.a);
+                        if constexpr (MET == GRAY_METRIC_DEFORMED)
+                            K.B = make_deformed(cm.a, cm.eps3);
+                        else
+                            K.B = make_spin(cm.a);
                         K.rbh = cm.rbh;
                         K.step_frac = A.step_frac;
                         K.xi_eps = A.xi_eps;
@@ -672,6 +684,11 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                             Kf.xi_eps = (float)(0.5 * A.xi_eps);
                             Kf.euler_inv = (float)A.euler_inv;
                             r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
+                            rcap_f = (float)(cm.rcap * (1.0 + 1e-6));
+                            rmark_f = (float)cm.rmark;
+                            rband_f = (float)(cm.rmark * (1.0 + 2.0 * A.step_frac));
+                            L.locked = xi_violated_at(Kf.B.a, Kf.B.a2, L.hi.r, L.s, L.c, L.hi.kt, L.hi.kr,
+                                                      L.hi.kth, L.hi.kph, Kf.xi_eps);
                         }
                         rcap = cm.rcap;
                         resc = A.r_escape;
@@ -710,11 +727,14 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
         if (active) {
             // Equatorial-crossing recorder and 2 r_bh mark of one accepted
             // step from xp to x (each a rare event, tested wave-wide first).
-            auto record = [&](const State<double> &xp, const State<double> &x) {
-                const bool cross = record_disk && !hit && (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0;
+            // Equatorial-crossing recorder of one accepted step from
+            // (pth, pr, pph) to x, and the 2 r_bh mark, each a rare event
+            // tested wave-wide first.
+            auto record_disk_event = [&](double pth, double pr, double pph, const State<double> &x) {
+                const bool cross = record_disk && !hit && (pth - kHalfPi) * (x.th - kHalfPi) < 0.0;
                 if (record_disk && __builtin_expect(any_lane(cross), 0) && cross) {
-                    const double f = (kHalfPi - xp.th) / (x.th - xp.th);
-                    const double rc = xp.r + f * (x.r - xp.r);
+                    const double f = (kHalfPi - pth) / (x.th - pth);
+                    const double rc = pr + f * (x.r - pr);
                     // recorder window of the photon's camera, read when needed
                     const DevCam &cw = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
                     if (rc >= cw.disk_rmin && rc <= cw.disk_rmax) {
@@ -724,61 +744,93 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                         Column<double> D(GRAY_ARG(disk), A.stride, id);
                         D.put(rc);
                         D.next();
-                        D.put(xp.ph + f * (x.ph - xp.ph));
+                        D.put(pph + f * (x.ph - pph));
                         D.next();
                         D.put(disk_redshift(K.B.a, rc, E, Lz));
                         hit = true;
                     }
                 }
-                const double rmark = K.rbh + K.rbh;
-                const bool inward = xp.r >= rmark && x.r < rmark;
-                if (record_mark && __builtin_expect(any_lane(inward), 0) && inward) {
-                    const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
-                    Column<double> M(GRAY_ARG(mark), A.stride, id);
-                    for (int k = 0; k < 8; ++k) {
-                        M.put(v[k]);
-                        if (k < 7) M.next();
-                    }
+            };
+            auto write_mark = [&](const State<double> &xp) {
+                const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
+                Column<double> M(GRAY_ARG(mark), A.stride, id);
+                for (int k = 0; k < 8; ++k) {
+                    M.put(v[k]);
+                    if (k < 7) M.next();
                 }
             };
-            State<double> x;
+            auto record = [&](const State<double> &xp, const State<double> &x) {
+                record_disk_event(xp.th, xp.r, xp.ph, x);
+                const double rmark = K.rbh + K.rbh;
+                const bool inward = xp.r >= rmark && x.r < rmark;
+                if (record_mark && __builtin_expect(any_lane(inward), 0) && inward) write_mark(xp);
+            };
             int fl;
+            int32_t st = GRAY_RUNNING;
             if constexpr (P == GRAY_FP64) {
                 fl = rk4_step<PM>(K, L.x, L.s, L.c, record);
-                x = L.x;
+                const State<double> &x = L.x;
+                st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
+                st = (x.r > resc && x.kr > 0.0) ? GRAY_ESCAPED : st;
+                st = x.r < rcap ? GRAY_CAPTURED : st;
+                st = (fl < 0 || !finite_state(x)) ? GRAY_NONFINITE : st;
             } else {
-                const State<double> xp = L.value();
                 auto &F = L;
-                const bool need64 = F.hi.r < r64 || F.s < (float)A.fp64_pole ||
-                                    fabsf(F.hi.kr) < (float)A.fp64_turn * fabsf(F.hi.kt);
+                // The step runs in FP64 near the horizon, a pole or a radial
+                // turning point, and when the state itself fails the float
+                // guard of the null monitor (an Euler-locked photon, whose
+                // float proposals would all be rejected).
+                const bool need64 = F.hi.r < r64 || F.s < pole_f || fabsf(F.hi.kr) < turn_f * fabsf(F.hi.kt) ||
+                                    F.locked;
+                // A photon at r in [2 r_bh, 2 r_bh (1 + 2 Delta)) may fall below
+                // 2 r_bh in this step (a step moves r by at most about Delta r):
+                // its state is kept as the mark before a float step.
+                const bool band = record_mark && !need64 && F.hi.r >= rmark_f && F.hi.r < rband_f;
+                if (__builtin_expect(any_lane(band), 0) && band) write_mark(F.value());
+                const float pth = F.hi.th, pr = F.hi.r, pph = F.hi.ph;
                 fl = -2;
-                if (!need64) fl = rk4_step_c32(Kf, F.hi, F.lo, F.s, F.c, Kf.xi_eps);
-                if (fl == -2) {
-                    // FP64 step of the FP32C kernel: sin/cos coefficients in
-                    // vector registers (its scalar registers are the scarce ones)
-                    x = xp;
+                if (any_lane(!need64) && !need64) fl = rk4_step_c32(Kf, F.hi, F.lo, F.s, F.c, Kf.xi_eps);
+                const bool flt = fl >= 0;
+                if (__builtin_expect(any_lane(fl == -2), 0) && fl == -2) {
+                    // FP64 step of the FP32C kernel
+                    State<double> x = F.value();
                     double s64, c64;
                     sin_cos<false>(x.th, s64, c64);
-                    fl = rk4_step<kPoleMonitor, false>(K, x, s64, c64);
+                    fl = rk4_step<kPoleMonitor, false>(K, x, s64, c64, record);
                     if (fl >= 0) {
                         F.set(x);
                         ++n64;
+                        F.locked = xi_violated_at(Kf.B.a, Kf.B.a2, F.hi.r, F.s, F.c, F.hi.kt, F.hi.kr, F.hi.kth,
+                                                  F.hi.kph, Kf.xi_eps);
                     }
                 }
-                x = F.value();
-                if (fl >= 0) record(xp, x);
+                if (flt) F.locked = false;   // an accepted float proposal passed the guard
+                if (record_disk && flt) {
+                    const bool cross = !hit && (pth - (float)kHalfPi) * (F.hi.th - (float)kHalfPi) <= 0.0f;
+                    if (__builtin_expect(any_lane(cross), 0) && cross)
+                        record_disk_event(pth, pr, pph, F.value());
+                }
+                // Termination tests on the float high words, exact (hi + lo in
+                // FP64) only for photons within a relative 1e-6 of a threshold.
+                st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
+                const bool near = F.hi.r < rcap_f || (F.hi.r > resc_f && F.hi.kr >= 0.0f);
+                if (__builtin_expect(any_lane(near), 0) && near) {
+                    const double xr = (double)F.hi.r + (double)F.lo.r;
+                    const double xkr = (double)F.hi.kr + (double)F.lo.kr;
+                    st = (xr > resc && xkr > 0.0) ? GRAY_ESCAPED : st;
+                    st = xr < rcap ? GRAY_CAPTURED : st;
+                }
+                const bool finite = isfinite(F.hi.t) && isfinite(F.hi.r) && isfinite(F.hi.th) &&
+                                    isfinite(F.hi.ph) && isfinite(F.hi.kt) && isfinite(F.hi.kr) &&
+                                    isfinite(F.hi.kth) && isfinite(F.hi.kph);
+                st = (fl < 0 || !finite) ? GRAY_NONFINITE : st;
             }
-            // status after the step, taken with selects (no per-lane branch)
+            // counters after the step, taken with selects (no per-lane branch)
             const bool ok = fl >= 0;
             nsteps += ok;
             ncall += ok;
             ne += ok ? (fl & 1) : 0;
             nr += ok ? ((fl >> 1) & 1) : 0;
-            int32_t st = GRAY_RUNNING;
-            st = nsteps >= A.max_steps ? GRAY_UNFINISHED : st;
-            st = (x.r > resc && x.kr > 0.0) ? GRAY_ESCAPED : st;
-            st = x.r < rcap ? GRAY_CAPTURED : st;
-            st = (!ok || !finite_state(x)) ? GRAY_NONFINITE : st;
             const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
             if (__builtin_expect(any_lane(stop), 0) && stop) {
                 const ArgPointers PA = arg_pointers<1>();
@@ -939,10 +991,11 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassArgs A)
         double alpha, beta;
         pixel_of(c, i, alpha, beta);
         State<double> x0;
-        camera_state(c.a, c.r_obs, c.incl, alpha, beta, x0);
+        const bool deformed = c.metric == GRAY_METRIC_DEFORMED;
+        camera_state(c.a, c.r_obs, c.incl, alpha, beta, x0, c.eps3, deformed);
         double E0, L0, Q0, E, L, Q;
-        conserved(c.a, x0, E0, L0, Q0);
-        conserved(c.a, xf, E, L, Q);
+        conserved_in(c.a, c.eps3, deformed, x0, E0, L0, Q0);
+        conserved_in(c.a, c.eps3, deformed, xf, E, L, Q);
         State<double> xd = xf;
         if (st == GRAY_CAPTURED && A.mark && A.mark[1 * S + i] > 0.0) {
             xd.t = A.mark[0 * S + i]; xd.r = A.mark[1 * S + i];
@@ -951,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(ClassArgs A)
             xd.kth = A.mark[6 * S + i]; xd.kph = A.mark[7 * S + i];
         }
         double Ed, Ld, Qd;
-        conserved(c.a, xd, Ed, Ld, Qd);
+        conserved_in(c.a, c.eps3, deformed, xd, Ed, Ld, Qd);
         double *C = A.cons;
         C[0 * S + i] = E0;
         C[1 * S + i] = L0;
@@ -994,6 +1047,15 @@ static bool camera_physical_ok(const gray_camera &c)
 {
     if (c.kind != GRAY_CAMERA_GRID && c.kind != GRAY_CAMERA_POLAR) return false;
     if (!(c.a >= 0.0 && c.a < 1.0)) return false;
+    if (c.metric == GRAY_METRIC_KERR) {
+        if (c.deform != 0.0) return false;
+    } else if (c.metric == GRAY_METRIC_DEFORMED) {
+        // regular outside the Kerr horizon: 1 + h > 0 and Delta + a^2 sin^2 h > 0
+        if (!std::isfinite(c.deform)) return false;
+        if (!(c.deform >= 0.0 || (c.a == 0.0 && c.deform > -8.0))) return false;
+    } else {
+        return false;
+    }
     if (!(c.r_obs > horizon_radius(c.a) && std::isfinite(c.r_obs))) return false;
     if (!(c.incl >= 0.0 && c.incl <= kPi)) return false;
     return std::isfinite(c.alpha_lo) && std::isfinite(c.alpha_hi) && std::isfinite(c.beta_lo) &&
@@ -1032,6 +1094,26 @@ static int validate_cameras(const gray_camera *cams, int32_t ncam, int64_t n, ui
         if (next > n) return GRAY_EINVAL;
     }
     return next == n ? GRAY_OK : GRAY_EINVAL;
+}
+
+// The spacetime of a call: every camera (every non-empty slot) must use the
+// same metric kind; the deformed metric is served in FP64 with the
+// production pole treatment and without the disk recorder. Call after
+// validate_cameras.
+static int call_metric(const gray_camera *cams, int32_t ncam, const gray_params *p, int *metric)
+{
+    int m = -1;
+    for (int32_t k = 0; k < ncam; ++k) {
+        if ((int64_t)cams[k].nx * cams[k].ny == 0) continue;
+        if (m < 0) m = cams[k].metric;
+        else if (cams[k].metric != m) return GRAY_EUNSUPPORTED;
+    }
+    if (m < 0) m = GRAY_METRIC_KERR;
+    if (m == GRAY_METRIC_DEFORMED &&
+        (p->precision != GRAY_FP64 || p->pole_mode != GRAY_POLE_MONITOR || (p->flags & GRAY_RECORD_DISK)))
+        return GRAY_EUNSUPPORTED;
+    *metric = m;
+    return GRAY_OK;
 }
 
 static int validate_state(const gray_state *s, const gray_params *p)
@@ -1074,6 +1156,8 @@ static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool sl
         o.ny = c.ny;
         o.index = k0 + j;
         o.kind = c.kind;
+        o.metric = c.metric;
+        o.eps3 = c.deform;
         lo = std::min(lo, c.first);
         hi = std::max(hi, c.first + m);
     }
@@ -1083,16 +1167,17 @@ static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool sl
 }
 
 // Integrator variants: FP64 with each pole treatment, FP32C (production
-// treatment only).
-constexpr int kVariants = 4;
-static int variant_of(const gray_params *p)
+// treatment only), FP64 in the deformed metric (production treatment only).
+constexpr int kVariants = 5;
+static int variant_of(const gray_params *p, int metric)
 {
+    if (metric == GRAY_METRIC_DEFORMED) return 4;
     return p->precision == GRAY_FP32C ? 1 : (p->pole_mode == GRAY_POLE_MONITOR ? 0 : 1 + p->pole_mode);
 }
 
 struct DeviceInfo {
     int cus = 0;
-    int blocks_per_cu[kVariants] = {0, 0, 0, 0};
+    int blocks_per_cu[kVariants] = {0, 0, 0, 0, 0};
 };
 static std::mutex g_dev_mutex;
 static DeviceInfo g_dev[64];
@@ -1111,7 +1196,8 @@ static int device_info(DeviceInfo &out)
         if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
         const void *kernels[kVariants] = {
             (const void *)k_integrate<GRAY_FP64, kPoleMonitor>, (const void *)k_integrate<GRAY_FP32C, kPoleMonitor>,
-            (const void *)k_integrate<GRAY_FP64, kPoleEulerCrossing>, (const void *)k_integrate<GRAY_FP64, kPoleNone>};
+            (const void *)k_integrate<GRAY_FP64, kPoleEulerCrossing>, (const void *)k_integrate<GRAY_FP64, kPoleNone>,
+            (const void *)k_integrate<GRAY_FP64, kPoleMonitor, GRAY_METRIC_DEFORMED>};
         for (int v = 0; v < kVariants; ++v) {
             int nb = 0;
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[v], kBlock, 0);
@@ -1196,6 +1282,8 @@ extern "C" int gray_camera_init(const gray_camera *cams, int32_t ncam, const gra
     if ((e = validate_state(s, p))) return e;
     if (s->n == 0) return GRAY_OK;
     if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
+    int metric = 0;
+    if ((e = call_metric(cams, ncam, p, &metric))) return e;
     hipStream_t st = (hipStream_t)hip_stream;
     for (int32_t k0 = 0; k0 < ncam; k0 += kCamChunk)
         if ((e = launch_init(cams, k0, ncam - k0 < kCamChunk ? ncam - k0 : kCamChunk, p, s, st))) return e;
@@ -1212,24 +1300,20 @@ extern "C" int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int3
     if (s->n == 0) return GRAY_EINVAL;
     if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
     if (slot < 0 || slot >= ncam || (int64_t)cams[slot].nx * cams[slot].ny == 0) return GRAY_EINVAL;
+    int metric = 0;
+    if ((e = call_metric(cams, ncam, p, &metric))) return e;
     return launch_init(cams, slot, 1, p, s, (hipStream_t)hip_stream);
 }
 
-extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
-                              void *workspace, size_t workspace_bytes, void *hip_stream)
+// Body of gray_integrate and gray_integrate_static once the arguments and
+// the workspace have been checked: `workspace` is device memory of at least
+// ws_layout(n, ncam, flags).total bytes, 256-byte aligned. Every byte the
+// kernels read from it is written first by k_setup and the ordering passes
+// of the same call, so its previous contents do not matter.
+static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s, int metric,
+                             void *workspace, const DeviceInfo &dev, hipStream_t st)
 {
-    int e = validate_params(p);
-    if (e) return e;
-    if ((e = validate_state(s, p))) return e;
-    if (s->n == 0) return GRAY_OK;
-    if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
-    if (!workspace || ((uintptr_t)workspace & 255u) != 0 ||
-        workspace_bytes < gray_workspace_size(s->n, ncam, p))
-        return GRAY_EWORKSPACE;
-
-    DeviceInfo dev;
-    if ((e = device_info(dev))) return e;
-    hipStream_t st = (hipStream_t)hip_stream;
+    int e = GRAY_OK;
     const bool wl = (p->flags & GRAY_WORKLIST) != 0;
     const WsLayout W = ws_layout(s->n, ncam, p->flags);
     char *ws = (char *)workspace;
@@ -1251,6 +1335,7 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
             d.rmark = 2.0 * d.rbh;
             d.disk_rmin = p->disk_rmin < 0.0 ? isco_radius(c.a) : p->disk_rmin;
             d.disk_rmax = p->disk_rmax;
+            d.eps3 = c.deform;
         }
         hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, hdr,
                            wl ? s->work_out_count : (unsigned *)nullptr, ch);
@@ -1319,7 +1404,7 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     A.call_steps = p->call_steps;
     A.flags = p->flags;
     A.refill = 1;
-    const int variant = variant_of(p);
+    const int variant = variant_of(p, metric);
     const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[variant];
     // In work-list mode the list length is only known on the device; the grid
     // is capped at kMaxListWaves waves, which bounds the unused list tail.
@@ -1329,9 +1414,38 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     case 0: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
     case 1: hipLaunchKernelGGL((k_integrate<GRAY_FP32C, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
     case 2: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleEulerCrossing>), dim3(grid), dim3(kBlock), 0, st, A); break;
-    default: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 3: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    default:
+        hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleMonitor, GRAY_METRIC_DEFORMED>), dim3(grid), dim3(kBlock), 0, st,
+                           A);
+        break;
     }
     return check_launch("integrate launch");
+}
+
+static int validate_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p, const gray_state *s,
+                              int *metric)
+{
+    int e = validate_params(p);
+    if (e) return e;
+    if ((e = validate_state(s, p))) return e;
+    if (s->n == 0) return GRAY_OK;
+    if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
+    return call_metric(cams, ncam, p, metric);
+}
+
+extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
+                              void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    int metric = 0;
+    int e = validate_integrate(cams, ncam, p, s, &metric);
+    if (e || s->n == 0) return e;
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0 ||
+        workspace_bytes < gray_workspace_size(s->n, ncam, p))
+        return GRAY_EWORKSPACE;
+    DeviceInfo dev;
+    if ((e = device_info(dev))) return e;
+    return integrate_checked(cams, ncam, p, s, metric, workspace, dev, (hipStream_t)hip_stream);
 }
 
 extern "C" int gray_classify(const gray_camera *cams, int32_t ncam, const gray_params *p, const gray_state *s,
@@ -1343,6 +1457,8 @@ extern "C" int gray_classify(const gray_camera *cams, int32_t ncam, const gray_p
     if (!out) return GRAY_EINVAL;
     if (s->n == 0) return GRAY_OK;
     if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
+    int metric = 0;
+    if ((e = call_metric(cams, ncam, p, &metric))) return e;
     if (!out->flag) return GRAY_EINVAL;
     const bool wl = (p->flags & GRAY_WORKLIST) != 0;
     if (wl && (out->xf || out->cons)) return GRAY_EINVAL;
@@ -1395,7 +1511,7 @@ extern "C" const char *gray_strerror(int code)
     }
 }
 
-extern "C" int gray_version(void) { return 103; }
+extern "C" int gray_version(void) { return 200; }
 
 extern "C" size_t gray_struct_size(int which)
 {

@@ -235,14 +235,17 @@ GRAY_HD void sincos_small(float d, float &sd, float &cd)
     cd = fma(z, fma(z, 0.0416666679084301f, -0.5f), 1.0f);
 }
 
-// sin and cos of a moderate float angle: reduction by pi/2 with a two-term
-// float split of pi/2, then Taylor series on |r| <= pi/4 (sin to r^9, cos to
-// r^10: truncation below 3e-9).
-GRAY_HD void sincos_full(float x, float &s, float &c)
+// sin and cos of a moderate float angle x + lo (lo a low word below half an
+// ulp of x, or 0): reduction of x by pi/2 with a two-term float split of
+// pi/2, the low word added to the reduced argument (so an angle held as
+// hi + lo keeps its digits next to pi), then Taylor series on |r| <= pi/4
+// (sin to r^9, cos to r^10: truncation below 3e-9).
+GRAY_HD void sincos_full_lo(float x, float lo, float &s, float &c)
 {
     const float k = rintf(x * 0.6366197466850281f);
     float r = fma(-k, 1.5707963705062866f, x);
     r = fma(-k, -4.371138828673793e-08f, r);
+    r = r + lo;
     const float z = r * r;
     float ps = fma(z, 2.7557318844628753e-06f, -0.00019841270113829523f);
     ps = fma(z, ps, 0.008333333767950535f);
@@ -259,6 +262,8 @@ GRAY_HD void sincos_full(float x, float &s, float &c)
     s = (q & 2) ? -a : a;
     c = ((q + 1) & 2) ? -b : b;
 }
+
+GRAY_HD void sincos_full(float x, float &s, float &c) { sincos_full_lo(x, 0.0f, s, c); }
 
 GRAY_HD void sin_cos(float x, float &s, float &c) { sincos_full(x, s, c); }
 
@@ -302,16 +307,18 @@ GRAY_HD Spin<T> make_spin(T a)
 //   a^2 k^t^2 - 2 a rho^2 k^t k^phi + a^2 sin^2 rho^2 k^phi^2
 //                                       = Sigma^2 X^2 - rho^2 Sigma k^phi^2.
 // At2 and Aph2 are half of the lowered components A_t and A_phi / sin^2.
+// Given Delta = r^2 - 2 r + a^2 (the float step passes it in factored form,
+// (r - r_+)(r - r_-) with r - r_+ from the compensated state, which keeps its
+// digits next to the horizon).
 template <class T>
-GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr,
-                   T &dkth, T &dkph)
+GRAY_HD void accel_del(const Spin<T> &B, T r, T del, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr,
+                       T &dkth, T &dkph)
 {
     const T a = B.a, a2 = B.a2;
     const T r2 = r * r;
     const T s2 = s * s;
     const T sc = s * c;
     const T sig = fma(a2, c * c, r2);
-    const T del = fma(r, r - T(2), a2);
     const T rho2 = r2 + a2;
     const T sd = sig * del;
     const T i3 = rcp(sd * s);
@@ -355,9 +362,18 @@ GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T 
     dkph = fma(fma(T(2), q, T(-1)), Aph2, aq2 * At2) * idel2;
 }
 
-// f(y) of the geodesic equation given sin and cos of y.th.
 template <class T>
-GRAY_HD void deriv(const Spin<T> &B, const State<T> &y, T s, T c, State<T> &f)
+GRAY_HD void accel(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr,
+                   T &dkth, T &dkph)
+{
+    const T del = fma(r, r - T(2), B.a2);
+    accel_del<T>(B, r, del, s, c, kt, kr, kth, kph, dkt, dkr, dkth, dkph);
+}
+
+// f(y) of the geodesic equation given sin and cos of y.th, in the spacetime
+// B describes (Spin<T>: Kerr; DeformedSpin: the deformed metric below).
+template <class T, class SP>
+GRAY_HD void deriv(const SP &B, const State<T> &y, T s, T c, State<T> &f)
 {
     f.t = y.kt;
     f.r = y.kr;
@@ -412,12 +428,11 @@ GRAY_HD Metric<T> metric(T a, T a2, T r, T s, T c)
 //   g_rr Sigma Delta = Sigma^2,   g_thth Sigma Delta = Sigma^2 Delta,
 //   g_phph Sigma Delta = (rho^2 Sigma + 2 a^2 r sin^2) sin^2 Delta.
 template <class T>
-GRAY_HD bool xi_violated_at(T a, T a2, T r, T s, T c, T kt, T kr, T kth, T kph, T eps)
+GRAY_HD bool xi_violated_del(T a, T a2, T r, T del, T s, T c, T kt, T kr, T kth, T kph, T eps)
 {
     const T s2 = s * s;
     const T r2 = r * r;
     const T sig = fma(a2, c * c, r2);
-    const T del = fma(r, r - T(2), a2);
     const T sig2 = sig * sig;
     const T ar2 = (a + a) * r;                           // 2 a r
     const T phph = fma(ar2 * a, s2, (r2 + a2) * sig);    // rho^2 Sigma + 2 a^2 r sin^2
@@ -428,14 +443,140 @@ GRAY_HD bool xi_violated_at(T a, T a2, T r, T s, T c, T kt, T kr, T kth, T kph, 
     return fabs(num + den) > eps * fabs(den);
 }
 
+template <class T>
+GRAY_HD bool xi_violated_at(T a, T a2, T r, T s, T c, T kt, T kr, T kth, T kph, T eps)
+{
+    const T del = fma(r, r - T(2), a2);
+    return xi_violated_del<T>(a, a2, r, del, s, c, kt, kr, kth, kph, eps);
+}
+
+template <class T>
+GRAY_HD bool null_violated(const Spin<T> &B, T r, T s, T c, T kt, T kr, T kth, T kph, T eps)
+{
+    return xi_violated_at(B.a, B.a2, r, s, c, kt, kr, kth, kph, eps);
+}
+
+// ------------------------------------------------------- deformed Kerr metric
+// A non-Kerr spacetime of the kind Sec. 1 gives as the reason to integrate
+// the second-order geodesic equations (no Carter constant): the
+// Johannsen-Psaltis deformation of Kerr with deviation function
+// h = eps3 r / Sigma^2,
+//   g_tt   = -(1 + h)(1 - 2 r / Sigma),   g_tphi = -2 a (r / Sigma) sin^2 (1 + h),
+//   g_rr   = Sigma (1 + h) / (Delta + a^2 sin^2 h),   g_thth = Sigma,
+//   g_phph = sin^2 (r^2 + a^2 + 2 a^2 (r / Sigma) sin^2) + h a^2 (Sigma + 2 r) sin^4 / Sigma,
+// eps3 = 0 being Kerr. Its right-hand side is metric-generic: the metric is
+// evaluated once per call on numbers that carry their r and theta
+// derivatives (forward mode), and the lowered acceleration
+//   A_mu = (k^r d_r + k^th d_th)(g_mu b) k^b - 1/2 d_mu(g_ab) k^a k^b
+// (d_t = d_phi = 0) is raised with the inverse of the t-phi block.
+struct DeformedSpin {
+    double a, a2, eps3;
+};
+
+GRAY_HD DeformedSpin make_deformed(double a, double eps3) { return DeformedSpin{a, a * a, eps3}; }
+
+// A value with its derivatives by r and by theta.
+struct Dual2 {
+    double v, r, t;
+};
+GRAY_HD Dual2 operator+(Dual2 x, Dual2 y) { return Dual2{x.v + y.v, x.r + y.r, x.t + y.t}; }
+GRAY_HD Dual2 operator-(Dual2 x, Dual2 y) { return Dual2{x.v - y.v, x.r - y.r, x.t - y.t}; }
+GRAY_HD Dual2 operator+(double k, Dual2 y) { return Dual2{k + y.v, y.r, y.t}; }
+GRAY_HD Dual2 operator*(double k, Dual2 y) { return Dual2{k * y.v, k * y.r, k * y.t}; }
+GRAY_HD Dual2 operator*(Dual2 x, Dual2 y)
+{
+    return Dual2{x.v * y.v, fma(x.r, y.v, x.v * y.r), fma(x.t, y.v, x.v * y.t)};
+}
+GRAY_HD Dual2 rcp(Dual2 x)
+{
+    const double y = rcp(x.v);
+    const double m = -(y * y);
+    return Dual2{y, x.r * m, x.t * m};
+}
+
+// The five metric components, on plain doubles or on Dual2 (one expression
+// for both; only the operations defined for Dual2 are used).
+template <class N>
+struct MetricN {
+    N tt, tph, rr, thth, phph;
+};
+
+template <class N>
+GRAY_HD MetricN<N> deformed_metric(const DeformedSpin &B, N r, N s, N c)
+{
+    const N s2 = s * s;
+    const N r2 = r * r;
+    const N sig = r2 + B.a2 * (c * c);                 // Sigma
+    const N isig = rcp(sig);
+    const N q = r * isig;                              // r / Sigma
+    const N h = B.eps3 * (q * isig);                   // eps3 r / Sigma^2
+    const N h1 = 1.0 + h;
+    const N del = B.a2 + (r2 - 2.0 * r);               // Delta
+    MetricN<N> g;
+    g.tt = h1 * (-1.0 + 2.0 * q);
+    g.tph = (-2.0 * B.a) * ((q * s2) * h1);
+    g.rr = (sig * h1) * rcp(del + B.a2 * (s2 * h));
+    g.thth = sig;
+    const N F = B.a2 + (r2 + (2.0 * B.a2) * (q * s2)); // r^2 + a^2 + 2 a^2 q sin^2
+    g.phph = s2 * F + (B.a2 * h) * ((sig + 2.0 * r) * ((s2 * s2) * isig));
+    return g;
+}
+
+GRAY_HD void accel(const DeformedSpin &B, double r, double s, double c, double kt, double kr, double kth,
+                   double kph, double &dkt, double &dkr, double &dkth, double &dkph)
+{
+    const MetricN<Dual2> g = deformed_metric<Dual2>(B, Dual2{r, 1.0, 0.0}, Dual2{s, 0.0, c}, Dual2{c, 0.0, -s});
+    // derivative along the motion, k^r d_r + k^th d_th
+    const double Dtt = fma(kr, g.tt.r, kth * g.tt.t), Dtph = fma(kr, g.tph.r, kth * g.tph.t);
+    const double Drr = fma(kr, g.rr.r, kth * g.rr.t), Dthth = fma(kr, g.thth.r, kth * g.thth.t);
+    const double Dphph = fma(kr, g.phph.r, kth * g.phph.t);
+    const double At = fma(Dtt, kt, Dtph * kph);
+    const double Aph = fma(Dtph, kt, Dphph * kph);
+    // d_r and d_theta of g_ab k^a k^b
+    const double ktph2 = 2.0 * kt * kph, kt2 = kt * kt, kr2 = kr * kr, kth2 = kth * kth, kph2 = kph * kph;
+    double Qr = g.tt.r * kt2;
+    Qr = fma(g.tph.r, ktph2, Qr);
+    Qr = fma(g.rr.r, kr2, Qr);
+    Qr = fma(g.thth.r, kth2, Qr);
+    Qr = fma(g.phph.r, kph2, Qr);
+    double Qt = g.tt.t * kt2;
+    Qt = fma(g.tph.t, ktph2, Qt);
+    Qt = fma(g.rr.t, kr2, Qt);
+    Qt = fma(g.thth.t, kth2, Qt);
+    Qt = fma(g.phph.t, kph2, Qt);
+    const double Ar = fma(-0.5, Qr, Drr * kr);
+    const double Ath = fma(-0.5, Qt, Dthth * kth);
+    // inverse of the t-phi block: g^tt = g_phph / D2, g^tph = -g_tph / D2,
+    // g^phph = g_tt / D2 with D2 = g_tt g_phph - g_tph^2
+    const double iD2 = rcp(fma(g.tt.v, g.phph.v, -(g.tph.v * g.tph.v)));
+    dkt = -fma(g.phph.v, At, -(g.tph.v * Aph)) * iD2;
+    dkph = -fma(g.tt.v, Aph, -(g.tph.v * At)) * iD2;
+    dkr = -Ar * rcp(g.rr.v);
+    dkth = -Ath * rcp(g.thth.v);
+}
+
+// Null-condition test of eq. (4) in the deformed metric: |xi + 1| > eps with
+// xi the ratio of eq. (4), written |N + g_tt kt^2| > eps |g_tt kt^2|.
+GRAY_HD bool null_violated(const DeformedSpin &B, double r, double s, double c, double kt, double kr,
+                           double kth, double kph, double eps)
+{
+    const MetricN<double> g = deformed_metric<double>(B, r, s, c);
+    const double den = (g.tt * kt) * kt;
+    double num = g.rr * (kr * kr);
+    num = fma(g.thth, kth * kth, num);
+    num = fma(g.phph, kph * kph, num);
+    num = fma(2.0 * g.tph, kt * kph, num);
+    return fabs(num + den) > eps * fabs(den);
+}
+
 // Treatment of the polar axis (values of gray_pole_mode): the production
 // null-condition monitor, the earlier Euler step on pole crossings, or none.
 constexpr int kPoleMonitor = 0, kPoleEulerCrossing = 1, kPoleNone = 2;
 
-// Integrator constants of one photon.
-template <class T>
+// Integrator constants of one photon; SP describes the spacetime.
+template <class T, class SP = Spin<T>>
 struct StepConst {
-    Spin<T> B;
+    SP B;
     T rbh, step_frac, xi_eps;
     T euler_inv;   // 1 / (the Euler fallback's step divisor, 9 in Sec. 2)
 };
@@ -474,8 +615,8 @@ struct NoObserver {
     GRAY_HD void operator()(const S &, const S &) const {}
 };
 
-template <int PM = kPoleMonitor, bool SC = true, class T, class Obs = NoObserver>
-GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&observe = Obs())
+template <int PM = kPoleMonitor, bool SC = true, class T, class SP, class Obs = NoObserver>
+GRAY_HD int rk4_step(const StepConst<T, SP> &K, State<T> &x, T &s, T &c, Obs &&observe = Obs())
 {
     // eq. (2): h1 = Delta r / D1 with D1 = |k^r| + r (|k^th| + |k^ph|), and
     // h2 = (r - r_bh) / (2 |k^r|); h2 < h1 is decided without dividing.
@@ -520,7 +661,7 @@ GRAY_HD int rk4_step(const StepConst<T> &K, State<T> &x, T &s, T &c, Obs &&obser
     step_sin_cos<SC>(xn.th, sy, cy);
     bool viol = false;
     if constexpr (PM == kPoleMonitor) {
-        viol = xi_violated_at(K.B.a, K.B.a2, xn.r, sy, cy, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps);
+        viol = null_violated(K.B, xn.r, sy, cy, xn.kt, xn.kr, xn.kth, xn.kph, K.xi_eps);
     } else if constexpr (PM == kPoleEulerCrossing) {
         viol = xn.th > T(kPi) || xn.th < T(0);
     }
@@ -616,10 +757,198 @@ GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<floa
     return 0;
 }
 
+// The null monitor of eq. (4) in float with a bound on its own rounding:
+// returns 1 when |xi + 1| > eps holds (written |N + D| > eps |D| as in
+// xi_violated_del, N the numerator of xi, D = g_tt kt^2, both times
+// Sigma Delta), 0 when it fails, and -1 when the float evaluation cannot
+// decide: | |N + D| - eps |D| | is within 32 float roundings of the sum of the
+// magnitudes of the terms of N and D (they cancel to |xi + 1| |D| on a null
+// ray, by orders of magnitude next to the horizon, so a fixed guard band
+// would be either too wide far out or too narrow there).
+GRAY_HD int xi_violated_guarded(float a, float a2, float r, float del, float s, float c, float kt, float kr,
+                                float kth, float kph, float eps)
+{
+    const float s2 = s * s;
+    const float r2 = r * r;
+    const float sig = fma(a2, c * c, r2);
+    const float sig2 = sig * sig;
+    const float ar2 = (a + a) * r;
+    const float phph = fma(ar2 * a, s2, (r2 + a2) * sig);
+    const float t_th = sig2 * (kth * kth);
+    const float t_ph = phph * (s2 * kph) * kph;
+    const float t_x = -(ar2 + ar2) * (s2 * kt) * kph;
+    const float t_r = sig2 * (kr * kr);
+    const float num = fma(del, (t_th + t_ph) + t_x, t_r);
+    const float den = ((r + r - sig) * del) * (kt * kt);
+    const float mag = fma(fabsf(del), (fabsf(t_th) + fabsf(t_ph)) + fabsf(t_x), fabsf(t_r)) + fabsf(den);
+    const float margin = fabsf(num + den) - eps * fabsf(den);
+    if (!(fabsf(margin) > 1.9073486e-06f * mag)) return -1;   // 32 * 2^-24
+    return margin > 0.0f ? 1 : 0;
+}
+
+// Horizon radii of one photon's spacetime for the float step: r_+ as a
+// float pair (r_+ = rp_hi + rp_lo to about 1e-15) and r_- in float.
+struct FloatHorizon {
+    float rp_hi, rp_lo, rm;
+};
+
+GRAY_HD FloatHorizon make_float_horizon(double a)
+{
+    const double rp = 1.0 + sqrt(1.0 - a * a);
+    FloatHorizon H;
+    H.rp_hi = (float)rp;
+    H.rp_lo = (float)(rp - (double)H.rp_hi);
+    H.rm = (float)(2.0 - rp);
+    return H;
+}
+
+// Error-free sum when |a| >= |b| (or a = 0): s + e == a + b exactly.
+GRAY_HD void fast_two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    e = b - (s - a);
+}
+
+// pi as a float pair
+constexpr float kPiHi = 3.14159274101257324f, kPiLo = -8.74227765734758577e-08f;
+
+// One step of the production scheme (Sec. 2) in float arithmetic on the
+// compensated state hi + lo, written to keep the digits that plain float
+// loses: r - r_bh of eq. (2) and Delta = (r - r_+)(r - r_-) near the horizon
+// are formed from hi + lo (and the stage offsets h k^r), sin and cos of the
+// state's theta include its low word, and the stage angles are reached from
+// them through the offsets h k^theta (never through a rounded float theta),
+// which keeps cot and 1/sin^2 accurate next to the poles. The classical RK4
+// increment is added with TwoSum; the null monitor of eq. (4) is evaluated in
+// float on the proposal and a violation re-integrates with the forward-Euler
+// step h / euler_div, also compensated; the remap of eq. (3) is applied to
+// the float pair (theta compared with pi as a pair). Decisions are taken in
+// float: the monitor's |xi + 1| is reproduced to about 1e-6 relative, so a
+// decision can differ from the FP64 step's only for a proposal within that of
+// epsilon, and a proposal whose monitor float cannot decide (its rounding
+// bound, xi_violated_guarded) or that is not finite returns -2 with the
+// state kept, for the caller to take the step in FP64. Returns the flags of
+// rk4_step, -1 when h is not a positive finite number, or -2 (state kept in
+// both cases). (s, c) = sin/cos(hi.th + lo.th) on entry and exit.
+GRAY_HD int rk4_step_f32(const StepConst<float> &K, const FloatHorizon &H, State<float> &hi, State<float> &lo,
+                         float &s, float &c)
+{
+    const float dr = (hi.r - H.rp_hi) + (lo.r - H.rp_lo);   // r - r_bh
+    const float akr = fabsf(hi.kr);
+    const float D1 = fma(hi.r, fabsf(hi.kth) + fabsf(hi.kph), akr);
+    const float n1 = K.step_frac * hi.r;
+    const float d2 = akr + akr;
+    const bool second = (hi.kr != 0.0f) && (dr * D1 < d2 * n1);
+    const float h = second ? quot(dr, d2) : quot(n1, D1);
+    const bool hbad = !(h > 0.0f && h < INFINITY);
+    if (__builtin_expect(any_lane(hbad), 0))
+        if (hbad) return -1;
+    const float hh = 0.5f * h;
+
+    // stage derivatives summed as they come; k1 stays for the Euler fallback
+    State<float> k1, k, y, acc;
+    float sy, cy;
+    auto stage = [&](const State<float> &ks, float hs) {
+        y = axpy(hi, hs, ks);
+        const float ydr = fma(hs, ks.r, dr);
+        shift_sincos(s, c, hs * ks.th, y.th, sy, cy);
+        k.t = y.kt;
+        k.r = y.kr;
+        k.th = y.kth;
+        k.ph = y.kph;
+        accel_del<float>(K.B, y.r, ydr * (y.r - H.rm), sy, cy, y.kt, y.kr, y.kth, y.kph, k.kt, k.kr, k.kth, k.kph);
+    };
+    k1.t = hi.kt;
+    k1.r = hi.kr;
+    k1.th = hi.kth;
+    k1.ph = hi.kph;
+    accel_del<float>(K.B, hi.r, dr * (hi.r - H.rm), s, c, hi.kt, hi.kr, hi.kth, hi.kph, k1.kt, k1.kr, k1.kth, k1.kph);
+    stage(k1, hh);
+    acc = axpy(k1, 2.0f, k);
+    stage(k, hh);
+    acc = axpy(acc, 2.0f, k);
+    stage(k, h);
+
+    const float h6 = h * (1.0f / 6.0f);
+    State<float> nh, nl;
+#define GRAY_F32(cmp) two_sum(hi.cmp, fma(h6, acc.cmp + k.cmp, lo.cmp), nh.cmp, nl.cmp)
+    GRAY_F32(t); GRAY_F32(r); GRAY_F32(th); GRAY_F32(ph);
+    GRAY_F32(kt); GRAY_F32(kr); GRAY_F32(kth); GRAY_F32(kph);
+#undef GRAY_F32
+    int flags = 0;
+    sincos_full_lo(nh.th, nl.th, sy, cy);
+    const float ndr = (nh.r - H.rp_hi) + (nl.r - H.rp_lo);
+    const int vm = xi_violated_guarded(K.B.a, K.B.a2, nh.r, ndr * (nh.r - H.rm), sy, cy, nh.kt, nh.kr, nh.kth,
+                                       nh.kph, K.xi_eps);
+    // a decision float cannot take is left to the FP64 step (state kept)
+    const bool undecided = vm < 0 || !(isfinite(nh.t) && isfinite(nh.r) && isfinite(nh.th) && isfinite(nh.ph) &&
+                                       isfinite(nh.kt) && isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph));
+    if (__builtin_expect(any_lane(undecided), 0))
+        if (undecided) return -2;
+    const bool viol = vm > 0;
+    // theta - pi of the proposal as one float (exact difference next to pi)
+    bool up = (nh.th - kPiHi) + (nl.th - kPiLo) > 0.0f;
+    bool down = nh.th < 0.0f || (nh.th == 0.0f && nl.th < 0.0f);
+    if (__builtin_expect(any_lane(viol || up || down), 0)) {
+        if (viol) {
+            const float he = h * K.euler_inv;
+#define GRAY_F32E(cmp) two_sum(hi.cmp, fma(he, k1.cmp, lo.cmp), nh.cmp, nl.cmp)
+            GRAY_F32E(t); GRAY_F32E(r); GRAY_F32E(th); GRAY_F32E(ph);
+            GRAY_F32E(kt); GRAY_F32E(kr); GRAY_F32E(kth); GRAY_F32E(kph);
+#undef GRAY_F32E
+            flags |= 1;
+            up = (nh.th - kPiHi) + (nl.th - kPiLo) > 0.0f;
+            down = nh.th < 0.0f || (nh.th == 0.0f && nl.th < 0.0f);
+        }
+        if (up) {
+            // theta -> 2 pi - theta = pi - (theta - pi); phi -> phi + pi
+            const float d = (nh.th - kPiHi) + (nl.th - kPiLo);
+            two_sum(kPiHi, kPiLo - d, nh.th, nl.th);
+        } else if (down) {
+            nh.th = -nh.th;
+            nl.th = -nl.th;
+        }
+        if (up || down) {
+            const float sg = up ? 1.0f : -1.0f;
+            float ps, pe;
+            two_sum(nh.ph, sg * kPiHi, ps, pe);
+            fast_two_sum(ps, pe + (nl.ph + sg * kPiLo), nh.ph, nl.ph);
+            nh.kth = -nh.kth;
+            nl.kth = -nl.kth;
+            flags |= 2;
+        }
+        float sf, cf;
+        sincos_full_lo(nh.th, nl.th, sf, cf);
+        sy = flags ? sf : sy;
+        cy = flags ? cf : cy;
+    }
+    hi = nh;
+    lo = nl;
+    s = sy;
+    c = cy;
+    return flags;
+}
+
 // Initial state of the ray through image-plane point (alpha, beta) of an
 // observer at distance D and inclination incl (flat plane-parallel screen,
 // ray traced backwards: k = -p, p^t > 0 from the null condition).
-GRAY_HD void camera_state(double a, double D, double incl, double alpha, double beta, State<double> &x)
+// Metric components at (r, theta) of the camera's spacetime: Kerr, or the
+// deformed metric when `deformed` (deviation eps3).
+GRAY_HD Metric<double> metric_of(double a, double eps3, bool deformed, double r, double s, double c)
+{
+    if (!deformed) return metric(a, a * a, r, s, c);
+    const MetricN<double> d = deformed_metric<double>(make_deformed(a, eps3), r, s, c);
+    Metric<double> g;
+    g.tt = d.tt;
+    g.tph = d.tph;
+    g.rr = d.rr;
+    g.thth = d.thth;
+    g.phph = d.phph;
+    return g;
+}
+
+GRAY_HD void camera_state(double a, double D, double incl, double alpha, double beta, State<double> &x,
+                          double eps3 = 0.0, bool deformed = false)
 {
     double si, ci;
     sincos(incl, &si, &ci);
@@ -641,7 +970,7 @@ GRAY_HD void camera_state(double a, double D, double incl, double alpha, double 
     }
     double s0, c0;
     sincos(th0, &s0, &c0);
-    const Metric<double> g = metric(a, a * a, r0, s0, c0);
+    const Metric<double> g = metric_of(a, eps3, deformed, r0, s0, c0);
     const double S = g.rr * pr * pr + g.thth * pth * pth + g.phph * pph * pph;
     const double B = g.tph * pph;
     const double pt = (-B - sqrt(B * B - g.tt * S)) / g.tt;
@@ -657,13 +986,18 @@ GRAY_HD void camera_state(double a, double D, double incl, double alpha, double 
 
 // E = -p_t, L = p_phi, Q = p_th^2 + cos^2 (L^2 / sin^2 - a^2 E^2) of p = -k,
 // given s, c = sin, cos of x.th.
-GRAY_HD void conserved_sc(double a, const State<double> &x, double s, double c, double &E, double &L, double &Q)
+GRAY_HD void conserved_g(const Metric<double> &g, double a, const State<double> &x, double s, double c, double &E,
+                         double &L, double &Q)
 {
-    const Metric<double> g = metric(a, a * a, x.r, s, c);
     E = g.tt * x.kt + g.tph * x.kph;
     L = -(g.tph * x.kt + g.phph * x.kph);
     const double pth = -g.thth * x.kth;
     Q = pth * pth + c * c * (L * L / (s * s) - a * a * E * E);
+}
+
+GRAY_HD void conserved_sc(double a, const State<double> &x, double s, double c, double &E, double &L, double &Q)
+{
+    conserved_g(metric(a, a * a, x.r, s, c), a, x, s, c, E, L, Q);
 }
 
 GRAY_HD void conserved(double a, const State<double> &x, double &E, double &L, double &Q)
@@ -671,6 +1005,16 @@ GRAY_HD void conserved(double a, const State<double> &x, double &E, double &L, d
     double s, c;
     sincos(x.th, &s, &c);
     conserved_sc(a, x, s, c, E, L, Q);
+}
+
+// E and L_z in the camera's spacetime; Q is the Kerr expression, a constant
+// of motion only in Kerr (eps3 = 0 or not deformed).
+GRAY_HD void conserved_in(double a, double eps3, bool deformed, const State<double> &x, double &E, double &L,
+                          double &Q)
+{
+    double s, c;
+    sincos(x.th, &s, &c);
+    conserved_g(metric_of(a, eps3, deformed, x.r, s, c), a, x, s, c, E, L, Q);
 }
 
 // Redshift of light from a prograde Keplerian emitter at radius rc in the

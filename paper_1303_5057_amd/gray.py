@@ -41,13 +41,18 @@ GRAY_POLE_MONITOR, GRAY_POLE_EULER_CROSSING, GRAY_POLE_NONE = 0, 1, 2
 GRAY_CAMERA_GRID = 0
 GRAY_CAMERA_POLAR = 1
 
+# gray_camera.metric
+GRAY_METRIC_KERR = 0
+GRAY_METRIC_DEFORMED = 1
+
 
 class gray_camera(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("r_obs", ctypes.c_double), ("incl", ctypes.c_double),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("alpha_lo", ctypes.c_double), ("alpha_hi", ctypes.c_double),
                 ("beta_lo", ctypes.c_double), ("beta_hi", ctypes.c_double),
-                ("first", ctypes.c_int64), ("kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("first", ctypes.c_int64), ("kind", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("deform", ctypes.c_double)]
 
 
 class gray_params(ctypes.Structure):
@@ -78,7 +83,8 @@ class gray_result(ctypes.Structure):
 
 
 EXPORTS = ("gray_workspace_size", "gray_camera_init", "gray_camera_init_slot", "gray_integrate",
-           "gray_classify", "gray_strerror", "gray_version", "gray_struct_size")
+           "gray_classify", "gray_strerror", "gray_version",
+           "gray_struct_size")
 
 
 class GrayError(RuntimeError):
@@ -164,13 +170,17 @@ def gray_version() -> int:
 
 
 # ----------------------------------------------------------------- marshalling
+def camera_struct(c: Camera, first: int) -> gray_camera:
+    return gray_camera(c.a, c.r_obs, c.incl, c.nx, c.ny, c.alpha_lo, c.alpha_hi, c.beta_lo,
+                       c.beta_hi, first, c.kind, c.metric, c.deform)
+
+
 def camera_array(cams: Sequence[Camera]):
     """ctypes array of gray_camera tiling photon ids [0, n) in order."""
     arr = (gray_camera * len(cams))()
     first = 0
     for k, c in enumerate(cams):
-        arr[k] = gray_camera(c.a, c.r_obs, c.incl, c.nx, c.ny, c.alpha_lo, c.alpha_hi, c.beta_lo,
-                             c.beta_hi, first, c.kind, 0)
+        arr[k] = camera_struct(c, first)
         first += c.nx * c.ny
     return arr
 

@@ -143,7 +143,7 @@ class Server:
         self.p.flags |= G.GRAY_SLOTS | G.GRAY_WORKLIST
         self.slots = (G.gray_camera * self.max_slots)()
         for k in range(self.max_slots):
-            self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0)
+            self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0.0)
         ws = G.gray_workspace_size(S, self.max_slots, self.p)
         self._ws = torch.zeros(ws + 256, dtype=torch.uint8, device=dev)
         self.ws_ptr = self._ws.data_ptr() + (-self._ws.data_ptr()) % 256
@@ -181,8 +181,7 @@ class Server:
         if first is None:
             return False
         k = free_slots[0]
-        self.slots[k] = G.gray_camera(c.a, c.r_obs, c.incl, c.nx, c.ny, c.alpha_lo, c.alpha_hi,
-                                      c.beta_lo, c.beta_hi, first, c.kind, 0)
+        self.slots[k] = G.camera_struct(c, first)
         G.gray_camera_init_slot(self.slots, self.max_slots, k, self.p, self.state, self.stream)
         res = RequestResult(req.rid, req.arrival_s, admit_s=now, photons=n)
         self.active[k] = (req, first, n, res)
@@ -205,7 +204,7 @@ class Server:
             res.x = rows.cpu().numpy()
         # free the range: its photons stay terminal (status is not RUNNING)
         self.alloc.release(first, n)
-        self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0)
+        self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0.0)
         res.done_s = now
         return res
 

@@ -23,7 +23,8 @@ SEED_BASE = 20260000
 @dataclass(frozen=True)
 class Camera:
     """Kerr spin a, observer distance r_obs (M), inclination incl (radians),
-    and an nx x ny image-plane grid: kind 0, cell-centred over
+    spacetime (metric, deform), and an nx x ny image-plane grid: kind 0,
+    cell-centred over
     [alpha_lo, alpha_hi] x [beta_lo, beta_hi] (M); kind 1 (polar), nx
     cell-centred radii in [alpha_lo, alpha_hi] times ny angles from beta_lo
     to beta_hi inclusive (radians)."""
@@ -37,6 +38,10 @@ class Camera:
     beta_lo: float
     beta_hi: float
     kind: int = 0
+    # spacetime: 0 Kerr; 1 Kerr deformed by the Johannsen-Psaltis deviation
+    # function with parameter `deform` (epsilon_3)
+    metric: int = 0
+    deform: float = 0.0
 
     @property
     def n(self) -> int:

@@ -161,3 +161,15 @@ def isco_by_energy_minimum(a):
     res = optimize.minimize_scalar(lambda r: kerr_circular_energy(a, r), bounds=(lo, 12.0),
                                    method="bounded", options={"xatol": 1e-12})
     return res.x
+
+
+# ------------------------------------------- deformed Kerr metric, a = 0
+def deformed_static_critical_impact(eps3):
+    """Critical impact parameter of the a = 0 deformed metric, which is static
+    and spherically symmetric with -g_tt = f(r) = (1 + eps3 / r^3)(1 - 2 / r)
+    and g_thth = r^2: a null ray of impact parameter b has a turning point
+    where b^2 = r^2 / f(r), so it is captured iff b < min_{r > 2} r / sqrt(f)."""
+    f = lambda r: (1.0 + eps3 / r ** 3) * (1.0 - 2.0 / r)
+    res = optimize.minimize_scalar(lambda r: r / np.sqrt(f(r)), bounds=(2.05, 10.0), method="bounded",
+                                   options={"xatol": 1e-12})
+    return res.fun

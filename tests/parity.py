@@ -42,11 +42,14 @@ SKIP_LOCKED = {"fp64": False, "fp32c": True}
 NTHREADS = int(os.environ.get("ORACLE_THREADS", "0"))
 
 
-def oracle_params(p: W.Params):
+def oracle_params(p: W.Params, cam: W.Camera = None):
+    deformed = cam is not None and cam.metric == G.GRAY_METRIC_DEFORMED
     return oracle.make_params(step_frac=p.step_frac, horizon_eps=p.horizon_eps, r_escape=p.r_escape,
                               xi_eps=p.xi_eps, euler_div=p.euler_div, max_steps=p.max_steps,
                               record_disk=p.record_disk, disk_rmin=p.disk_rmin,
-                              disk_rmax=p.disk_rmax, pole_mode=p.pole_mode)
+                              disk_rmax=p.disk_rmax, pole_mode=p.pole_mode,
+                              metric=oracle.METRIC_JP if deformed else oracle.METRIC_KERR,
+                              eps3=cam.deform if deformed else 0.0)
 
 
 def pixel_ab(cam: W.Camera, ids):
@@ -70,14 +73,29 @@ class OracleRun:
 
 
 def run_oracle(cam: W.Camera, p: W.Params, ids=None) -> OracleRun:
+    """Oracle traces of the listed pixels. band_dist is the distance (M) of
+    each ray's asymptotic image-plane point to the critical curve: Bardeen's
+    curve in Kerr; for the deformed metric at a = 0 the circle of the
+    closed-form critical impact parameter; NaN where no closed form exists
+    (deformed, a > 0)."""
     if ids is None:
         ids = np.arange(cam.n)
     al, be = pixel_ab(cam, ids)
-    X0 = np.array([oracle.camera(cam.a, cam.r_obs, cam.incl, x, y) for x, y in zip(al, be)])
-    res = oracle.run(oracle_params(p), cam.a, X0, nthreads=NTHREADS, want_disk=p.record_disk)
-    cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
-    band = analytic.CriticalBand(cam.a, cam.incl)
-    d = band.distance(cons0[:, 0], cons0[:, 1], cons0[:, 2])
+    if cam.metric == G.GRAY_METRIC_DEFORMED:
+        X0 = np.array([oracle.camera_jp(cam.a, cam.deform, cam.r_obs, cam.incl, x, y) for x, y in zip(al, be)])
+        cons0 = np.array([oracle.conserved_jp(cam.a, cam.deform, x) for x in X0])
+    else:
+        X0 = np.array([oracle.camera(cam.a, cam.r_obs, cam.incl, x, y) for x, y in zip(al, be)])
+        cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
+    res = oracle.run(oracle_params(p, cam), cam.a, X0, nthreads=NTHREADS, want_disk=p.record_disk)
+    if cam.metric != G.GRAY_METRIC_DEFORMED or cam.deform == 0.0:
+        band = analytic.CriticalBand(cam.a, cam.incl)
+        d = band.distance(cons0[:, 0], cons0[:, 1], cons0[:, 2])
+    elif cam.a == 0.0:
+        b = np.sqrt(cons0[:, 1] ** 2 + cons0[:, 2]) / cons0[:, 0]
+        d = np.abs(b - analytic.deformed_static_critical_impact(cam.deform))
+    else:
+        d = np.full(len(ids), np.nan)
     return OracleRun(res.status, res.steps, res.x, res.n_euler, res.n_remap, res.disk, d, cons0)
 
 

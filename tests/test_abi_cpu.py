@@ -42,7 +42,7 @@ def test_struct_layouts(lib):
     for k, t in enumerate((G.gray_camera, G.gray_params, G.gray_state, G.gray_result)):
         assert lib.gray_struct_size(k) == ctypes.sizeof(t)
     assert lib.gray_struct_size(99) == 0
-    assert ctypes.sizeof(G.gray_camera) == 80
+    assert ctypes.sizeof(G.gray_camera) == 88
 
 
 def test_strerror_and_version(lib):
@@ -98,6 +98,11 @@ def test_invalid_params_rejected(lib, field, value):
     W.Camera(0.5, 1000.0, 3.5, 8, 8, -5, 5, -5, 5),       # inclination > pi
     W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, math.nan, -5, 5),
     W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, kind=2),             # unknown camera kind
+    W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, metric=2),           # unknown metric
+    W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, deform=1.0),         # Kerr with a deviation
+    W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, metric=1, deform=-0.1),  # spinning, eps3 < 0
+    W.Camera(0.0, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, metric=1, deform=-8.0),  # 1 + h = 0 at r = 2
+    W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, metric=1, deform=math.inf),
 ])
 def test_invalid_camera_rejected(lib, cam):
     p = G.params_struct(W.Params())
@@ -168,3 +173,25 @@ def test_camera_array_tiles_photon_ids():
     cams = [W.scaled(CAM, 3, 5), W.scaled(CAM, 7), W.scaled(CAM, 1)]
     arr = G.camera_array(cams)
     assert [arr[k].first for k in range(3)] == [0, 15, 64]
+
+
+def test_deformed_metric_requirements(lib):
+    """The deformed metric runs in FP64 with the production pole treatment and
+    no disk recorder, and all cameras of a call share one metric kind."""
+    dcam = W.Camera(0.5, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, metric=G.GRAY_METRIC_DEFORMED, deform=1.5)
+    s = _state(64, 64)
+    p = G.params_struct(W.Params())
+    for bad in (W.Params(pole_mode=G.GRAY_POLE_NONE), W.Params(record_disk=True)):
+        pb = G.params_struct(bad)
+        sb = G.gray_state(0x1000, None, 0x2000, 0x3000, 0x4000, None, None, 0x6000, 64, 64)
+        assert _call_init([dcam], pb, sb) == G.GRAY_EUNSUPPORTED
+        assert _call_integrate([dcam], pb, sb) == G.GRAY_EUNSUPPORTED
+    p32 = G.params_struct(W.Params(precision="fp32c"))
+    s32 = _state(64, 64, lo=0x9000)
+    assert _call_integrate([dcam], p32, s32) == G.GRAY_EUNSUPPORTED
+    s2 = _state(128, 128)
+    assert _call_init([dcam, CAM], p, s2) == G.GRAY_EUNSUPPORTED
+    assert _call_classify([CAM, dcam], p, s2) == G.GRAY_EUNSUPPORTED
+    # a = 0 admits a negative deviation while 1 + h stays positive outside r = 2
+    ok = W.Camera(0.0, 1000.0, 1.0, 8, 8, -5, 5, -5, 5, metric=G.GRAY_METRIC_DEFORMED, deform=-1.0)
+    assert _call_integrate([ok], p, _state(64, 64), ws=None) == G.GRAY_EWORKSPACE

@@ -18,8 +18,8 @@ independent of the oracle's code:
 """
 import numpy as np
 import pytest
-from scipy import optimize
 
+import analytic
 import oracle
 
 rng = np.random.default_rng(20261203)
@@ -107,20 +107,12 @@ def test_constants_along_deformed_rays(orc, eps3):
         assert max(dq) > 1e-4
 
 
-def _critical_impact(eps3):
-    """a = 0: min over r outside the horizon of r / sqrt(f(r))."""
-    f = lambda r: (1.0 + eps3 / r ** 3) * (1.0 - 2.0 / r)
-    res = optimize.minimize_scalar(lambda r: r / np.sqrt(f(r)), bounds=(2.05, 10.0), method="bounded",
-                                   options={"xatol": 1e-12})
-    return res.fun, res.x
-
-
 @pytest.mark.parametrize("eps3", [2.0, -1.0])
 def test_spherical_deformation_shadow_radius(orc, eps3):
     """a = 0, i = 60 deg, 48 x 48 over [-8, 8]^2: captured iff the ray's
     impact parameter sqrt(L^2 + Q) / E is below the critical value of the
     deformed static metric (rays within 2e-3 M of it are not checked)."""
-    bc, rph = _critical_impact(eps3)
+    bc = analytic.deformed_static_critical_impact(eps3)
     assert abs(bc - np.sqrt(27.0)) > 0.05          # the deformation moves the shadow
     n = 48
     ax = -8.0 + 16.0 * (np.arange(n) + 0.5) / n
