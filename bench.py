@@ -391,22 +391,25 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int, floor: boo
     euler = b.counters.view(3, b.stride)[0, : b.n].cpu().numpy()
     band = band_distance(cam, cons[0], cons[1], cons[2])
     drift = drift_groups(G, np, status, cons, euler, band)
+    # the pass's own results, copied before the floor measurement re-initialises the batch
+    host = {"status": status, "steps": b.steps[: b.n].cpu().numpy(),
+            "x": res.xf.view(8, b.stride)[:, : b.n].cpu().numpy().T if res.xf is not None else None,
+            "euler": euler, "band": band}
     tail = longest_alone(G, W, torch, np, b, params) if floor else None
-    xf = res.xf.view(8, b.stride)[:, : b.n].cpu().numpy().T if res.xf is not None else None
     return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
             "total_steps": total_steps, "status": np.bincount(status, minlength=5).tolist(),
             "euler_steps": counters[0], "fp64_steps": counters[2], "drift": drift, "n": b.n,
-            "lane_efficiency": lane_eff, "tail": tail,
-            "host": {"status": status, "steps": b.steps[: b.n].cpu().numpy(), "x": xf,
-                     "euler": euler, "band": band}}
+            "lane_efficiency": lane_eff, "tail": tail, "host": host}
 
 
 def band_distance(cam, E0, L0, Q0):
     """Distance (M) of each ray's asymptotic image-plane point, from its own
-    constants of motion at the camera, to the Kerr critical curve."""
+    constants of motion at the camera, to the Kerr critical curve; inf
+    beyond 0.1 M (every use compares it with 1e-3 or 1e-2 M, and the bounded
+    search keeps 16.8M rays to seconds)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import analytic
-    return analytic.CriticalBand(cam.a, cam.incl).distance(E0, L0, Q0)
+    return analytic.CriticalBand(cam.a, cam.incl).distance(E0, L0, Q0, upper=0.1)
 
 
 def drift_groups(G, np, status, cons, euler, band) -> dict:

@@ -99,11 +99,15 @@ class CriticalBand:
         if self.pole_on:
             self.radius = np.hypot(al[0], be[0])
 
-    def distance(self, E, L, Q):
+    def distance(self, E, L, Q, upper=np.inf):
+        """Distances; with a finite `upper`, those beyond it come back as inf
+        (a bounded search, fast on millions of rays)."""
         al, be = effective_impact(self.a, self.incl, np.asarray(E), np.asarray(L), np.asarray(Q))
         if self.pole_on:
-            return np.abs(al - self.radius)
-        d, _ = self.tree.query(np.column_stack([np.atleast_1d(al), np.atleast_1d(be)]))
+            d = np.abs(al - self.radius)
+            return np.where(d <= upper, d, np.inf)
+        d, _ = self.tree.query(np.column_stack([np.atleast_1d(al), np.atleast_1d(be)]),
+                               distance_upper_bound=upper, workers=-1)
         return d
 
 
