@@ -282,6 +282,22 @@ int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int32_t slot,
 int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p,
                    gray_state *s, void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * integration as gray_integrate, with the workspace taken from a static
+ * device array of GRAY_STATIC_WORKSPACE_BYTES that the library holds on each
+ * device it runs on until the process ends. The call allocates nothing; the
+ * caller still owns every buffer of `s`. Returns GRAY_EWORKSPACE when
+ * gray_workspace_size(s->n, ncam, p) exceeds GRAY_STATIC_WORKSPACE_BYTES
+ * (without GRAY_WORKLIST that is about 6.6M photons; with it, the camera
+ * table alone). Every call on one device shares that device's array, and
+ * the array keeps the last call's contents (each call rewrites what it
+ * reads): calls that overlap on one device, on different streams or from
+ * different threads, race and must be ordered by the caller. */
+#define GRAY_STATIC_WORKSPACE_BYTES (32u << 20)
+int gray_integrate_static(const gray_camera *cams, int32_t ncam, const gray_params *p,
+                          gray_state *s, void *hip_stream);
+
 /* Final classification and conservation diagnostics (E, L_z and Carter's Q,
  * Sec. 1) of every photon; see gray_result. */
 int gray_classify(const gray_camera *cams, int32_t ncam, const gray_params *p,

@@ -1210,6 +1210,35 @@ static int device_info(DeviceInfo &out)
     return GRAY_OK;
 }
 
+// Workspace of gray_integrate_static, for callers that cannot allocate:
+// one array per device, created with the code object and held until the
+// process ends. Host code must never pass `scratch` itself to a kernel (on
+// the host it names a stand-in, not device memory): static_scratch() looks
+// up the device address once per device and every launch uses that.
+static __device__ __align__(256) char scratch[GRAY_STATIC_WORKSPACE_BYTES];
+static std::mutex g_scratch_mutex;
+static void *g_scratch[64];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current).
+static int static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error("hipGetDevice", e);
+    if (dev < 0 || dev >= 64) return device_error("device index", hipErrorInvalidDevice);
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_error("hipGetSymbolAddress(scratch)", e);
+        if (!ptr || ((uintptr_t)ptr & 255u) != 0) return device_error("scratch address", hipErrorInvalidValue);
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return GRAY_OK;
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -1446,6 +1475,21 @@ extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_
     DeviceInfo dev;
     if ((e = device_info(dev))) return e;
     return integrate_checked(cams, ncam, p, s, metric, workspace, dev, (hipStream_t)hip_stream);
+}
+
+extern "C" int gray_integrate_static(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,
+                                     void *hip_stream)
+{
+    int metric = 0;
+    int e = validate_integrate(cams, ncam, p, s, &metric);
+    if (e || s->n == 0) return e;
+    const size_t need = gray_workspace_size(s->n, ncam, p);
+    if (need == 0 || need > (size_t)GRAY_STATIC_WORKSPACE_BYTES) return GRAY_EWORKSPACE;
+    DeviceInfo dev;
+    if ((e = device_info(dev))) return e;
+    void *ws = nullptr;
+    if ((e = static_scratch(&ws))) return e;
+    return integrate_checked(cams, ncam, p, s, metric, ws, dev, (hipStream_t)hip_stream);
 }
 
 extern "C" int gray_classify(const gray_camera *cams, int32_t ncam, const gray_params *p, const gray_state *s,

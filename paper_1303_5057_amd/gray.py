@@ -29,6 +29,8 @@ GRAY_RECORD_DISK = 1
 GRAY_SLOTS = 2
 GRAY_WORKLIST = 4
 GRAY_WORKLIST_SLACK = 1 << 20
+# size of the library's static per-device workspace (gray_integrate_static)
+GRAY_STATIC_WORKSPACE_BYTES = 32 << 20
 PRECISIONS = {"fp64": GRAY_FP64, "fp32c": GRAY_FP32C}
 
 
@@ -83,7 +85,7 @@ class gray_result(ctypes.Structure):
 
 
 EXPORTS = ("gray_workspace_size", "gray_camera_init", "gray_camera_init_slot", "gray_integrate",
-           "gray_classify", "gray_strerror", "gray_version",
+           "gray_integrate_static", "gray_classify", "gray_strerror", "gray_version",
            "gray_struct_size")
 
 
@@ -112,6 +114,7 @@ def load() -> ctypes.CDLL:
     L.gray_camera_init_slot.restype = ctypes.c_int
     L.gray_camera_init_slot.argtypes = [C, i32, i32, P, S, vp]
     L.gray_integrate.restype, L.gray_integrate.argtypes = ctypes.c_int, [C, i32, P, S, vp, sz, vp]
+    L.gray_integrate_static.restype, L.gray_integrate_static.argtypes = ctypes.c_int, [C, i32, P, S, vp]
     L.gray_classify.restype, L.gray_classify.argtypes = ctypes.c_int, [C, i32, P, S, R, vp]
     L.gray_strerror.restype, L.gray_strerror.argtypes = ctypes.c_char_p, [ctypes.c_int]
     L.gray_version.restype, L.gray_version.argtypes = ctypes.c_int, []
@@ -152,6 +155,11 @@ def gray_integrate(cams, ncam: int, p: gray_params, s: gray_state, workspace: in
     return _check("gray_integrate",
                   load().gray_integrate(cams, ncam, ctypes.byref(p), ctypes.byref(s), workspace,
                                         workspace_bytes, stream))
+
+
+def gray_integrate_static(cams, ncam: int, p: gray_params, s: gray_state, stream: int = 0) -> int:
+    return _check("gray_integrate_static",
+                  load().gray_integrate_static(cams, ncam, ctypes.byref(p), ctypes.byref(s), stream))
 
 
 def gray_classify(cams, ncam: int, p: gray_params, s: gray_state, out: gray_result,
@@ -263,6 +271,11 @@ class Batch:
     def integrate(self, stream: Optional[int] = None) -> None:
         gray_integrate(self.cam_arr, len(self.cams), self.p, self.state, self.ws_ptr, self.ws_bytes,
                        current_stream() if stream is None else stream)
+
+    def integrate_static(self, stream: Optional[int] = None) -> None:
+        """gray_integrate with the library's static workspace (no allocation)."""
+        gray_integrate_static(self.cam_arr, len(self.cams), self.p, self.state,
+                              current_stream() if stream is None else stream)
 
     def classify(self, xf: bool = True, cons: bool = True, counts: bool = True,
                  stream: Optional[int] = None) -> Result:

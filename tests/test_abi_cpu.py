@@ -161,6 +161,31 @@ def test_workspace_checked(lib):
     assert _call_integrate([CAM], p, s, wsb=need - 1) == G.GRAY_EWORKSPACE
 
 
+def test_static_workspace_limit(lib):
+    """gray_integrate_static rejects, on the host, a call whose workspace
+    would not fit the library's static array, and checks its arguments as
+    gray_integrate does."""
+    p = G.params_struct(W.Params())
+    cap = G.GRAY_STATIC_WORKSPACE_BYTES
+    # largest dense-mode photon count that fits, and one photon-chunk more
+    n_fit = 64
+    while G.gray_workspace_size(n_fit * 2, 1, p) <= cap:
+        n_fit *= 2
+    big = n_fit * 2
+    assert G.gray_workspace_size(big, 1, p) > cap
+    cam = W.Camera(0.5, 1000.0, 1.0, 64, big // 64, -5, 5, -5, 5)
+    s = _state(big, big)
+    arr = G.camera_array([cam])
+    assert lib.gray_integrate_static(arr, 1, ctypes.byref(p), ctypes.byref(s), None) == G.GRAY_EWORKSPACE
+    bad = G.params_struct(W.Params())
+    bad.step_frac = 0.0
+    s = _state(64, 64)
+    arr = G.camera_array([CAM])
+    assert lib.gray_integrate_static(arr, 1, ctypes.byref(bad), ctypes.byref(s), None) == G.GRAY_EINVAL
+    empty = G.gray_state(None, None, None, None, None, None, None, None, 0, 0)
+    assert lib.gray_integrate_static(arr, 1, ctypes.byref(p), ctypes.byref(empty), None) == G.GRAY_OK
+
+
 def test_empty_batch_is_a_no_op(lib):
     p = G.params_struct(W.Params())
     s = G.gray_state(None, None, None, None, None, None, None, None, 0, 0)
