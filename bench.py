@@ -37,6 +37,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 78.6}
 # Rays closer than this to the critical curve (M, on the ray's own constants of
 # motion) may legitimately differ in outcome between two correct integrators.
 BAND = 1e-3
+# Rays whose path comes closer than this (sin theta) to the polar axis carry
+# the largest RK4 truncation error of the scheme at Delta = 1/32; drift
+# statistics are also reported without them.
+AXIS_SIN = 0.02
 
 
 def measured_traffic(prec: str):
@@ -151,6 +155,20 @@ def serving(args) -> dict:
                           "photon_steps_per_s": sum(r.photon_steps for r in res) / wall,
                           "mean_photons_per_request": float(np.mean([r.photons for r in res])),
                           "max_in_flight": srv.max_active}}
+    # each size class's floor: a few of its requests served alone, one after
+    # the other, on an otherwise empty server
+    from paper_1303_5057_amd.serve import SIZE_CLASSES, size_class
+    floors = {}
+    for name, _, _ in SIZE_CLASSES:
+        picks = [r for r in closed if size_class(r.camera.nx * r.camera.ny) == name][:3]
+        lat = []
+        for r in picks:
+            one = srv.run([W.Request(r.rid, 0.0, r.camera)], realtime=False)
+            lat.append(one[0].latency_s * 1e3)
+        if lat:
+            floors[name] = {"requests": len(lat), "alone_ms": lat,
+                            "photons": [r.camera.nx * r.camera.ny for r in picks]}
+    out["alone_floor_by_size"] = floors
     for frac in (0.5, 0.9):
         reqs = W.request_stream(n, qps=frac * qps_sat)
         srv = Server(budget, params)
@@ -159,7 +177,8 @@ def serving(args) -> dict:
         out[f"load_{frac}"] = {"qps": frac * qps_sat, "p50_ms": st["p50_ms"],
                                "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
                                "photon_steps_per_s": st["photon_steps_per_s"],
-                               "max_in_flight": srv.max_active, "iterations": srv.iterations}
+                               "max_in_flight": srv.max_active, "iterations": srv.iterations,
+                               "by_size": st["by_size"]}
     return out
 
 
@@ -390,7 +409,7 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int, floor: boo
     cons = res.cons.view(9, b.stride)[:, : b.n].cpu().numpy()
     euler = b.counters.view(3, b.stride)[0, : b.n].cpu().numpy()
     band = band_distance(cam, cons[0], cons[1], cons[2])
-    drift = drift_groups(G, np, status, cons, euler, band)
+    drift = drift_groups(G, np, status, cons, euler, band, polar_turning(cam, cons[0], cons[1], cons[2]))
     # the pass's own results, copied before the floor measurement re-initialises the batch
     host = {"status": status, "steps": b.steps[: b.n].cpu().numpy(),
             "x": res.xf.view(8, b.stride)[:, : b.n].cpu().numpy().T if res.xf is not None else None,
@@ -412,12 +431,14 @@ def band_distance(cam, E0, L0, Q0):
     return analytic.CriticalBand(cam.a, cam.incl).distance(E0, L0, Q0, upper=0.1)
 
 
-def drift_groups(G, np, status, cons, euler, band) -> dict:
+def drift_groups(G, np, status, cons, euler, band, smin=None) -> dict:
     """Drift of E, L_z and Q (rows 6..8 of gray_classify's cons) per group of
     rays: outcome (escaped, captured) x position (outside or inside the 1e-3 M
     band around the critical curve) x Euler fallbacks (none, some). For each
     group: ray count, p50 / p99 / max of each drift, and how many rays exceed
-    1e-5 in each quantity."""
+    1e-5 in each quantity; with `smin` (sin theta at each ray's polar turning
+    point) also the same counts and maxima over the rays that stay off the
+    polar axis (smin >= 0.02)."""
     out = {}
     for oname, osel in (("escaped", status == G.ESCAPED), ("captured", status == G.CAPTURED)):
         for bname, bsel in (("outside_band", band > BAND), ("in_band", band <= BAND)):
@@ -429,8 +450,23 @@ def drift_groups(G, np, status, cons, euler, band) -> dict:
                     g.update({q: np.percentile(d, pq, axis=1).tolist()
                               for q, pq in (("p50", 50), ("p99", 99), ("max", 100))})
                     g["above_1e-5"] = (d > 1e-5).sum(axis=1).tolist()
+                if smin is not None:
+                    off = sel & (smin >= AXIS_SIN)
+                    do = cons[6:9, off]
+                    g["off_axis_rays"] = int(off.sum())
+                    if do.size:
+                        g["off_axis_max"] = do.max(axis=1).tolist()
+                        g["off_axis_above_1e-5"] = (do > 1e-5).sum(axis=1).tolist()
                 out[f"{oname}/{bname}/{ename}"] = g
     return out
+
+
+def polar_turning(cam, E0, L0, Q0):
+    """sin theta at each ray's polar turning point (closest approach to the
+    spin axis) from its constants of motion at the camera."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import analytic
+    return analytic.polar_turning_sin(cam.a, E0, L0, Q0)
 
 
 def longest_alone(G, W, torch, np, b, params, reps: int = 3) -> dict:
@@ -661,7 +697,8 @@ def c3_block(G, W, torch, np, with_oracle: bool, reps: int = 3) -> dict:
                "fp64_step_fraction": ctr[2] / steps, "euler_steps": ctr[0],
                "status_counts": np.bincount(status, minlength=5).tolist(),
                "disk_hit_fraction": float((disk_r > 0).float().mean().item()),
-               "drift_ELQ": drift_groups(G, np, status, cons, euler, band),
+               "drift_ELQ": drift_groups(G, np, status, cons, euler, band,
+                                         polar_turning(cam, cons[0], cons[1], cons[2])),
                "roofline": roofline(prec, m, None)}
         if ref is not None:
             # the sampled rays only, gathered on the device

@@ -37,8 +37,9 @@
  *   status int32[n]  gray_status of each photon.
  *   steps  int32[n]  accepted steps taken so far.
  *   cam    int32[n]  camera index of each photon (written by camera_init).
- *   counters  optional int32, 3 rows of `stride`: Euler fallbacks (eq. 4),
+ *   counters  int32, 3 rows of `stride`: Euler fallbacks (eq. 4),
  *          theta remaps (eq. 3), steps taken in FP64 (GRAY_FP32C; 0 else).
+ *          Optional, except for gray_integrate in GRAY_FP32C.
  *   mark   optional double, 8 rows of `stride`: the last accepted state with
  *          r >= 2 r_bh before the photon last fell below 2 r_bh (drift
  *          diagnostics for captured photons; r = 0 if never marked).
@@ -80,8 +81,13 @@ typedef enum {
 
 typedef enum {
     GRAY_FP64 = 0,  /* all arithmetic in double                               */
-    GRAY_FP32C = 1  /* float stages, compensated (hi + lo) state update, and
-                       double steps near the horizon and turning points       */
+    GRAY_FP32C = 1  /* float steps on a compensated (hi + lo) state; a photon
+                       continues in double precision once it enters a zone
+                       named in gray_params (near the horizon, a pole, a
+                       radial turning point) or once a float step cannot
+                       decide the null monitor of eq. (4). Requires the
+                       counters array (its FP64-step count marks those
+                       photons, so a later call continues them in FP64).  */
 } gray_precision;
 
 typedef enum {
@@ -192,9 +198,11 @@ typedef struct {
     double euler_div;    /* Euler fallback step h / euler_div; 9 in Sec. 2  >= 1 */
     double disk_rmin;    /* recorder window [rmin, rmax]; rmin < 0: r_ISCO(a)     */
     double disk_rmax;
-    /* GRAY_FP32C only: a step runs in double precision while any of these
-     * holds (near the horizon, near a pole, near a radial turning point);
-     * all >= 0, e.g. 1, 0.05, 0.01.                                          */
+    /* GRAY_FP32C only: a photon continues in double precision from the
+     * first step at which any of these holds (near the horizon, near a pole,
+     * near a radial turning point); all >= 0, 0 disables a zone; e.g.
+     * 0.02, 0.05, 0 (float rounding near the horizon and the poles is
+     * amplified by 1/Delta and 1/sin^2 theta).                                */
     double fp64_horizon; /* r < r_bh (1 + fp64_horizon)                          */
     double fp64_pole;    /* sin(theta) < fp64_pole                                */
     double fp64_turn;    /* |k^r| < fp64_turn |k^t|                               */

@@ -512,8 +512,7 @@ struct Lane<GRAY_FP64> {
 template <>
 struct Lane<GRAY_FP32C> {
     State<float> hi, lo;
-    float s, c;
-    bool locked;   // the state fails the float guard of the null monitor
+    float s, c;   // sin and cos of hi.th + lo.th
     __device__ __forceinline__ void load(const void *hp, const void *lp, int64_t S, int64_t id)
     {
         Column<const float> H((const float *)hp, S, id), L((const float *)lp, S, id);
@@ -528,7 +527,7 @@ struct Lane<GRAY_FP32C> {
         }
         hi.t = h[0]; hi.r = h[1]; hi.th = h[2]; hi.ph = h[3]; hi.kt = h[4]; hi.kr = h[5]; hi.kth = h[6]; hi.kph = h[7];
         lo.t = l[0]; lo.r = l[1]; lo.th = l[2]; lo.ph = l[3]; lo.kt = l[4]; lo.kr = l[5]; lo.kth = l[6]; lo.kph = l[7];
-        sin_cos(hi.th, s, c);
+        sincos_full_lo(hi.th, lo.th, s, c);
     }
     __device__ __forceinline__ void store(void *hp, void *lp, int64_t S, int64_t id) const
     {
@@ -553,15 +552,49 @@ struct Lane<GRAY_FP32C> {
         x.kth = (double)hi.kth + (double)lo.kth; x.kph = (double)hi.kph + (double)lo.kph;
         return x;
     }
-    __device__ __forceinline__ void set(const State<double> &x)
+    // hi + lo nearest x (to about 48 bits), without sin/cos
+    __device__ __forceinline__ void split(const State<double> &x)
     {
 #define GRAY_SPLIT(cmp) hi.cmp = (float)x.cmp; lo.cmp = (float)(x.cmp - (double)hi.cmp)
         GRAY_SPLIT(t); GRAY_SPLIT(r); GRAY_SPLIT(th); GRAY_SPLIT(ph);
         GRAY_SPLIT(kt); GRAY_SPLIT(kr); GRAY_SPLIT(kth); GRAY_SPLIT(kph);
 #undef GRAY_SPLIT
-        sin_cos(hi.th, s, c);
+    }
+    __device__ __forceinline__ void set(const State<double> &x)
+    {
+        split(x);
+        sincos_full_lo(hi.th, lo.th, s, c);
     }
 };
+
+// x rounded to the nearest sum of two floats, the form in which the FP32C
+// state is stored.
+__device__ __forceinline__ State<double> pair_rounded(const State<double> &x)
+{
+    Lane<GRAY_FP32C> P;
+    P.split(x);
+    return P.value();
+}
+
+// FP64 step of the FP32C integrator (x in, the accepted state out; flags as
+// rk4_step). Rare (a null-monitor decision that float rounding cannot take,
+// a non-finite float proposal, or a caller-requested FP64 zone), so it is a
+// real call: the float loop then keeps the registers of the float step
+// only, and the call saves and restores what it clobbers.
+struct Step64 {
+    State<double> x;
+    int flags;
+};
+
+__device__ __noinline__ Step64 fp64_step(StepConst<double> K, State<double> x)
+{
+    double s, c;
+    sin_cos<false>(x.th, s, c);
+    Step64 out;
+    out.flags = rk4_step<kPoleMonitor, false>(K, x, s, c);
+    out.x = x;
+    return out;
+}
 
 __device__ __forceinline__ bool finite_state(const State<double> &x)
 {
@@ -580,7 +613,7 @@ __device__ __forceinline__ bool finite_state(const State<double> &x)
 // carries no code for the others; MET selects the spacetime (Kerr, or the
 // deformed metric through the metric-generic right-hand side).
 template <int P, int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR>
-__global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRAY_FP32C ? 3 : 1))) void k_integrate(IntArgs A)
 {
     static_assert(MET == GRAY_METRIC_KERR || (P == GRAY_FP64 && PM == kPoleMonitor),
                   "the deformed metric is integrated in FP64 with the production pole treatment");
@@ -596,6 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     Lane<P> L;
     StepConst<double, Space> K;
     StepConst<float> Kf;
+    FloatHorizon Hf{};
     double rcap = 0.0, resc = 0.0;
     // FP32C: float thresholds of the photon (FP64 zone, capture and mark
     // radii, the mark band) and of the call (pole, turning point, escape)
@@ -681,14 +715,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                             Kf.B = make_spin((float)cm.a);
                             Kf.rbh = (float)cm.rbh;
                             Kf.step_frac = (float)A.step_frac;
-                            Kf.xi_eps = (float)(0.5 * A.xi_eps);
+                            Kf.xi_eps = (float)A.xi_eps;
                             Kf.euler_inv = (float)A.euler_inv;
+                            Hf = make_float_horizon(cm.a);
                             r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
                             rcap_f = (float)(cm.rcap * (1.0 + 1e-6));
                             rmark_f = (float)cm.rmark;
                             rband_f = (float)(cm.rmark * (1.0 + 2.0 * A.step_frac));
-                            L.locked = xi_violated_at(Kf.B.a, Kf.B.a2, L.hi.r, L.s, L.c, L.hi.kt, L.hi.kr,
-                                                      L.hi.kth, L.hi.kph, Kf.xi_eps);
                         }
                         rcap = cm.rcap;
                         resc = A.r_escape;
@@ -776,12 +809,12 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 st = (fl < 0 || !finite_state(x)) ? GRAY_NONFINITE : st;
             } else {
                 auto &F = L;
-                // The step runs in FP64 near the horizon, a pole or a radial
-                // turning point, and when the state itself fails the float
-                // guard of the null monitor (an Euler-locked photon, whose
-                // float proposals would all be rejected).
-                const bool need64 = F.hi.r < r64 || F.s < pole_f || fabsf(F.hi.kr) < turn_f * fabsf(F.hi.kt) ||
-                                    F.locked;
+                // The step is taken in float (rk4_step_f32); in FP64 when the
+                // float step cannot decide the null monitor (or its proposal
+                // is not finite), and, if the caller asks for it, inside the
+                // optional zones near the horizon, a pole or a radial turning
+                // point.
+                const bool need64 = F.hi.r < r64 || F.s < pole_f || fabsf(F.hi.kr) < turn_f * fabsf(F.hi.kt);
                 // A photon at r in [2 r_bh, 2 r_bh (1 + 2 Delta)) may fall below
                 // 2 r_bh in this step (a step moves r by at most about Delta r):
                 // its state is kept as the mark before a float step.
@@ -789,22 +822,18 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 if (__builtin_expect(any_lane(band), 0) && band) write_mark(F.value());
                 const float pth = F.hi.th, pr = F.hi.r, pph = F.hi.ph;
                 fl = -2;
-                if (any_lane(!need64) && !need64) fl = rk4_step_c32(Kf, F.hi, F.lo, F.s, F.c, Kf.xi_eps);
+                if (any_lane(!need64) && !need64) fl = rk4_step_f32(Kf, Hf, F.hi, F.lo, F.s, F.c);
                 const bool flt = fl >= 0;
                 if (__builtin_expect(any_lane(fl == -2), 0) && fl == -2) {
-                    // FP64 step of the FP32C kernel
-                    State<double> x = F.value();
-                    double s64, c64;
-                    sin_cos<false>(x.th, s64, c64);
-                    fl = rk4_step<kPoleMonitor, false>(K, x, s64, c64, record);
+                    const State<double> x0 = F.value();
+                    Step64 r64s = fp64_step(K, x0);
+                    fl = r64s.flags;
                     if (fl >= 0) {
-                        F.set(x);
+                        record(x0, r64s.x);
+                        F.set(r64s.x);
                         ++n64;
-                        F.locked = xi_violated_at(Kf.B.a, Kf.B.a2, F.hi.r, F.s, F.c, F.hi.kt, F.hi.kr, F.hi.kth,
-                                                  F.hi.kph, Kf.xi_eps);
                     }
                 }
-                if (flt) F.locked = false;   // an accepted float proposal passed the guard
                 if (record_disk && flt) {
                     const bool cross = !hit && (pth - (float)kHalfPi) * (F.hi.th - (float)kHalfPi) <= 0.0f;
                     if (__builtin_expect(any_lane(cross), 0) && cross)
@@ -893,6 +922,522 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                 }
             }
         }
+    }
+}
+
+// ---------------------------------------------- compensated-float integrator
+// The FP32C integrator. Each block has kBlock / kWave waves: all but the last
+// run photons in float steps (rk4_step_f32) on the compensated state; the
+// last runs FP64 steps. A photon goes over to FP64 for the rest of its path
+// when it enters a zone the caller names (near the horizon, near a pole, at
+// a radial turning point), or when the float step cannot decide the null
+// monitor of eq. (4) (its proposal lies within float rounding of epsilon),
+// and stays there: the counter of FP64 steps marks it, so a resumed call
+// continues it in FP64 too. The float waves hand such photons to their
+// block's FP64 wave through a small queue in LDS (state, step counts and
+// recorder flag per slot), so neither kind of wave carries the other's
+// code path or registers. While no photon waits for it, the FP64 wave runs
+// float photons too, a few at a time (it takes new ones only while fewer
+// than kHelperLimit photons wait, and returns to FP64 steps once its lanes
+// are empty), so it is not idle where no photon needs FP64. Each phase is a
+// loop of its own: no state is carried from one to the other.
+constexpr int kHandCap = 128;            // hand-off slots per block
+constexpr unsigned kFloatQuota = 64;     // slots the float waves may fill; the
+                                         // rest takes the FP64 wave's own
+                                         // hand-offs, so it never waits
+constexpr unsigned kHelperLimit = 1;     // photons waiting, from which on the
+                                         // FP64 wave takes no float work
+
+struct HandQueue {
+    unsigned head;        // slots taken by the FP64 wave (monotonic)
+    unsigned tail;        // slots reserved by the float waves (monotonic)
+    unsigned float_done;  // float waves of the block that have exited
+    unsigned ready[kHandCap];
+    int32_t id[kHandCap], nsteps[kHandCap], ncall[kHandCap], ne[kHandCap], nr[kHandCap], n64[kHandCap],
+        hit[kHandCap];
+    float hi[8][kHandCap], lo[8][kHandCap];
+};
+
+__device__ __forceinline__ unsigned lds_load(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store(unsigned *p, unsigned v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Stop bookkeeping shared by both loops: work-list output of the photons
+// still running and the per-camera completion counts (wave-uniform call).
+struct StopBook {
+    unsigned span_next = 0, span_end = 0;
+    __device__ __forceinline__ void account(bool stop_now, bool keep, int64_t id, unsigned lane, bool list_out,
+                                            bool count_done)
+    {
+        if (list_out) {
+            const uint64_t m = ballot(keep);
+            const unsigned cnt = (unsigned)__popcll(m);
+            if (cnt) {
+                const unsigned room = span_end - span_next;
+                unsigned fresh = 0;
+                if (cnt > room) {
+                    if (lane == 0) fresh = atomicAdd(GRAY_ARG(work_out_count), kSpan);
+                    fresh = __builtin_amdgcn_readfirstlane(fresh);
+                }
+                const unsigned r = lane_rank(m);
+                if (keep) glob(GRAY_ARG(work_out))[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
+                if (cnt > room) {
+                    span_next = fresh + (cnt - room);
+                    span_end = fresh + kSpan;
+                } else {
+                    span_next += cnt;
+                }
+            }
+        }
+        if (count_done) {
+            const bool fin = stop_now && !keep;
+            const uint64_t mf = ballot(fin);
+            if (mf) {
+                const int32_t c = fin ? glob(GRAY_ARG(cam))[id] : -1;
+                const unsigned lead = (unsigned)(__ffsll((long long)mf) - 1);
+                const int32_t cl = __shfl(c, (int)lead, kWave);
+                if (ballot(fin && c != cl) == 0ull) {
+                    if (lane == lead) atomicAdd(GRAY_ARG(cam_done) + cl, (unsigned)__popcll(mf));
+                } else if (fin) {
+                    atomicAdd(GRAY_ARG(cam_done) + c, 1u);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void finish(unsigned lane, bool list_out, unsigned long long iters)
+    {
+        if (list_out) {
+            global_ptr<int32_t> wo = glob(GRAY_ARG(work_out));
+            for (unsigned j = span_next + lane; j < span_end; j += kWave) wo[j] = -1;
+        }
+        if (unsigned long long *wi = GRAY_ARG(wave_iters))
+            if (lane == 0 && iters) atomicAdd(wi, iters);
+    }
+};
+
+// Store one photon's counters and state at a stop (either loop).
+__device__ __forceinline__ void c32_store(const Lane<GRAY_FP32C> &L, int64_t id, int32_t st, int32_t nsteps,
+                                          int32_t ne, int32_t nr, int32_t n64, int64_t S)
+{
+    const ArgPointers PA = arg_pointers<1>();
+    L.store(PA.x, PA.lo, S, id);
+    glob(PA.status)[id] = st;
+    glob(PA.steps)[id] = nsteps;
+    Column<int32_t> C(PA.counters, S, id);
+    C.put(ne);
+    C.next();
+    C.put(nr);
+    C.next();
+    C.put(n64);
+}
+
+// What a wave keeps from one phase to the next.
+struct WaveCtx {
+    bool exhausted = false;        // the global queue has nothing left for it
+    unsigned long long iters = 0;  // loop iterations with a stepping lane
+    StopBook book;
+};
+
+// Float phase: the persistent loop of k_integrate with the float step. The
+// float waves run it once, for their whole life; the FP64 wave runs it as a
+// helper (HELPER): it takes ids only as many as it has idle lanes and only
+// while fewer than kHelperLimit photons wait for FP64, and the phase ends
+// once its lanes are empty.
+template <bool HELPER>
+__device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, unsigned nfloat_waves, WaveCtx &W)
+{
+    const unsigned lane = threadIdx.x & (kWave - 1);
+    const bool record_disk = (A.flags & GRAY_RECORD_DISK) != 0;
+    const bool record_mark = A.mark != nullptr;
+    const bool list_out = A.work_out != nullptr;
+    const bool count_done = A.cam_done != nullptr;
+
+    bool active = false, pending = false;
+    int64_t id = 0;
+    Lane<GRAY_FP32C> L;
+    StepConst<float> Kf;
+    FloatHorizon Hf{};
+    float r64 = 0.0f, rcap_f = 0.0f, rmark_f = 0.0f, rband_f = 0.0f;
+    const float pole_f = (float)A.fp64_pole, turn_f = (float)A.fp64_turn;
+    const float resc_f = (float)(A.r_escape * (1.0 - 1e-6));
+    double rcap = 0.0;
+    int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
+    bool hit = false;
+
+    unsigned chunk_next = 0, chunk_end = 0;
+    bool &exhausted = W.exhausted;
+    // (the helper takes from the tail, where the launch order puts the
+    // photons expected to be shortest, so its phases end soon)
+    const bool from_tail =
+        A.two_ended && (HELPER || (__builtin_amdgcn_s_getreg(4 | (3 << 11)) & 15u) != 0u);
+    const int64_t nq = (int64_t)__builtin_amdgcn_readfirstlane(*A.work_in_count);
+    const int64_t waves = (int64_t)gridDim.x * nfloat_waves;
+    int64_t rounds = nq / (waves * kQueueChunk * 4);
+    rounds = rounds < 1 ? 1 : (rounds > kMaxGrab ? kMaxGrab : rounds);
+    StopBook &book = W.book;
+    unsigned long long &iters = W.iters;
+
+    for (;;) {
+        const uint64_t idle = ballot(!active);
+        // the helper takes float work only while few photons wait for it
+        const bool may_take = !HELPER || lds_load(&Q.tail) - lds_load(&Q.head) < kHelperLimit;
+        if (HELPER && idle == ~0ull && (!may_take || exhausted)) break;
+        if (__popcll(idle) >= A.refill || idle == ~0ull) {
+            // a helper grabs as many ids as it has idle lanes, so it leaves
+            // no ids behind when its phase ends
+            const unsigned grab = HELPER ? (unsigned)__popcll(idle) : (unsigned)rounds * kQueueChunk;
+            if (chunk_next >= chunk_end && !exhausted && may_take) {
+                unsigned long long old = 0;
+                if (lane == 0)
+                    old = atomicAdd(GRAY_ARG(queue), from_tail ? (unsigned long long)grab << 32 : (unsigned long long)grab);
+                const int64_t h = __builtin_amdgcn_readfirstlane((unsigned)old);
+                const int64_t t = __builtin_amdgcn_readfirstlane((unsigned)(old >> 32));
+                const int64_t end = nq - t;
+                if (h + t + grab >= nq) exhausted = true;
+                int64_t lo = h, hi = h;
+                if (end > h) {
+                    if (from_tail) {
+                        hi = end;
+                        lo = end - grab > h ? end - grab : h;
+                    } else {
+                        hi = h + grab < end ? h + grab : end;
+                    }
+                }
+                chunk_next = (unsigned)lo;
+                chunk_end = (unsigned)hi;
+            }
+            const unsigned avail = chunk_end - chunk_next;
+            if (avail > 0) {
+                const unsigned rank = lane_rank(idle);
+                const ArgPointers PA = arg_pointers<2>();
+                const int64_t S = A.stride;
+                if (!active && rank < avail) {
+                    const unsigned q = chunk_next + rank;
+                    id = (int64_t)glob(PA.work_in)[q];
+                    if (id >= 0 && glob(PA.status)[id] == GRAY_RUNNING) {
+                        L.load(PA.x, PA.lo, S, id);
+                        const DevCam cm = PA.cams[glob(PA.cam)[id]];
+                        Kf.B = make_spin((float)cm.a);
+                        Kf.rbh = (float)cm.rbh;
+                        Kf.step_frac = (float)A.step_frac;
+                        Kf.xi_eps = (float)A.xi_eps;
+                        Kf.euler_inv = (float)A.euler_inv;
+                        Hf = make_float_horizon(cm.a);
+                        r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
+                        rcap_f = (float)(cm.rcap * (1.0 + 1e-6));
+                        rmark_f = (float)cm.rmark;
+                        rband_f = (float)(cm.rmark * (1.0 + 2.0 * A.step_frac));
+                        rcap = cm.rcap;
+                        nsteps = glob(PA.steps)[id];
+                        ncall = 0;
+                        Column<int32_t> C(PA.counters, S, id);
+                        ne = C.get();
+                        C.next();
+                        nr = C.get();
+                        C.next();
+                        n64 = C.get();
+                        hit = record_disk && glob(PA.disk)[id] != 0.0;
+                        active = true;
+                        pending = n64 > 0;   // it continues in FP64
+                    }
+                }
+                const unsigned taken = __popcll(idle) < avail ? (unsigned)__popcll(idle) : avail;
+                chunk_next += taken;
+            }
+            if (!HELPER && exhausted && chunk_next >= chunk_end && ballot(active) == 0ull) {
+                book.finish(lane, list_out, iters);
+                if (lane == 0)
+                    __hip_atomic_fetch_add(&Q.float_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                break;
+            }
+        }
+
+        bool stop_now = false, keep = false;
+        iters += ballot(active && !pending) != 0ull;
+        if (active && !pending) {
+            auto &F = L;
+            const bool need64 = F.hi.r < r64 || F.s < pole_f || fabsf(F.hi.kr) < turn_f * fabsf(F.hi.kt);
+            // A photon at r in [2 r_bh, 2 r_bh (1 + 2 Delta)) may fall below
+            // 2 r_bh in this step (a step moves r by at most about Delta r):
+            // its state is kept as the mark before a float step.
+            const bool band = record_mark && !need64 && F.hi.r >= rmark_f && F.hi.r < rband_f;
+            if (__builtin_expect(any_lane(band), 0) && band) {
+                const State<double> xm = F.value();
+                const double v[8] = {xm.t, xm.r, xm.th, xm.ph, xm.kt, xm.kr, xm.kth, xm.kph};
+                Column<double> M(GRAY_ARG(mark), A.stride, id);
+                for (int k = 0; k < 8; ++k) {
+                    M.put(v[k]);
+                    if (k < 7) M.next();
+                }
+            }
+            const float pth = F.hi.th, pr = F.hi.r, pph = F.hi.ph;
+            int fl = -2;
+            if (any_lane(!need64) && !need64) fl = rk4_step_f32(Kf, Hf, F.hi, F.lo, F.s, F.c);
+            pending = fl == -2;
+            if (!pending) {
+                if (record_disk && fl >= 0) {
+                    const bool cross = !hit && (pth - (float)kHalfPi) * (F.hi.th - (float)kHalfPi) <= 0.0f;
+                    if (__builtin_expect(any_lane(cross), 0) && cross) {
+                        const State<double> x = F.value();
+                        const double ppth = pth, ppr = pr, ppph = pph;
+                        const double f = (kHalfPi - ppth) / (x.th - ppth);
+                        const double rc = ppr + f * (x.r - ppr);
+                        const DevCam &cw = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
+                        if (rc >= cw.disk_rmin && rc <= cw.disk_rmax) {
+                            double E, Lz, Qc, sx, cx;
+                            sin_cos<false>(x.th, sx, cx);
+                            conserved_sc(cw.a, x, sx, cx, E, Lz, Qc);
+                            Column<double> D(GRAY_ARG(disk), A.stride, id);
+                            D.put(rc);
+                            D.next();
+                            D.put(ppph + f * (x.ph - ppph));
+                            D.next();
+                            D.put(disk_redshift(cw.a, rc, E, Lz));
+                            hit = true;
+                        }
+                    }
+                }
+                // Termination tests on the float high words, exact (hi + lo
+                // in FP64) only for photons within a relative 1e-6 of a threshold.
+                int32_t st = GRAY_RUNNING;
+                st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
+                const bool near = F.hi.r < rcap_f || (F.hi.r > resc_f && F.hi.kr >= 0.0f);
+                if (__builtin_expect(any_lane(near), 0) && near) {
+                    const double xr = (double)F.hi.r + (double)F.lo.r;
+                    const double xkr = (double)F.hi.kr + (double)F.lo.kr;
+                    st = (xr > A.r_escape && xkr > 0.0) ? GRAY_ESCAPED : st;
+                    st = xr < rcap ? GRAY_CAPTURED : st;
+                }
+                const bool finite = __builtin_isfinite(F.hi.t) && __builtin_isfinite(F.hi.r) &&
+                                    __builtin_isfinite(F.hi.th) && __builtin_isfinite(F.hi.ph) &&
+                                    __builtin_isfinite(F.hi.kt) && __builtin_isfinite(F.hi.kr) &&
+                                    __builtin_isfinite(F.hi.kth) && __builtin_isfinite(F.hi.kph);
+                st = (fl < 0 || !finite) ? GRAY_NONFINITE : st;
+                const bool ok = fl >= 0;
+                nsteps += ok;
+                ncall += ok;
+                ne += ok ? (fl & 1) : 0;
+                nr += ok ? ((fl >> 1) & 1) : 0;
+                const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
+                if (__builtin_expect(any_lane(stop), 0) && stop) {
+                    c32_store(L, id, st, nsteps, ne, nr, n64, A.stride);
+                    stop_now = true;
+                    keep = st == GRAY_RUNNING;
+                    active = false;
+                }
+            }
+        }
+        book.account(stop_now, keep, id, lane, list_out, count_done);
+
+        // Photons that continue in FP64 go to the block's FP64 wave: reserve
+        // slots (all of them or none this iteration, by compare-and-swap on
+        // the reservation counter), fill them, then publish each slot.
+        const uint64_t pm = ballot(active && pending);
+        if (__builtin_expect(pm != 0ull, 0)) {
+            const unsigned k = (unsigned)__popcll(pm);
+            unsigned base = 0, ok = 0;
+            if (lane == 0) {
+                const unsigned t = lds_load(&Q.tail);
+                const unsigned h = lds_load(&Q.head);
+                if (t - h + k <= (HELPER ? (unsigned)kHandCap : kFloatQuota) && atomicCAS(&Q.tail, t, t + k) == t) {
+                    base = t;
+                    ok = 1;
+                }
+            }
+            ok = __builtin_amdgcn_readfirstlane(ok);
+            if (ok) {
+                base = __builtin_amdgcn_readfirstlane(base);
+                if (active && pending) {
+                    const unsigned s = (base + lane_rank(pm)) % kHandCap;
+                    Q.id[s] = (int32_t)id;
+                    Q.nsteps[s] = nsteps;
+                    Q.ncall[s] = ncall;
+                    Q.ne[s] = ne;
+                    Q.nr[s] = nr;
+                    Q.n64[s] = n64;
+                    Q.hit[s] = hit;
+                    const float *h = &L.hi.t, *l = &L.lo.t;
+                    for (int c = 0; c < 8; ++c) {
+                        Q.hi[c][s] = h[c];
+                        Q.lo[c][s] = l[c];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    lds_store(&Q.ready[s], 1u);
+                    active = false;
+                    pending = false;
+                }
+            } else if (pm == ballot(active)) {
+                __builtin_amdgcn_s_sleep(2);   // every busy lane waits for a slot
+            }
+        }
+    }
+}
+
+// FP64 phase of a block's FP64 wave: photons handed over by the block's
+// waves, FP64 steps on the compensated pair (the state is rounded to hi + lo
+// after every step, so a resumed call continues bit for bit), until they
+// stop. Returns true when the wave is done (the float waves of its block
+// have exited and every handed-over photon has stopped), false when it has
+// nothing to do but the global queue may still hold float work.
+__device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, unsigned nfloat_waves, WaveCtx &W)
+{
+    const unsigned lane = threadIdx.x & (kWave - 1);
+    const bool record_disk = (A.flags & GRAY_RECORD_DISK) != 0;
+    const bool record_mark = A.mark != nullptr;
+    const bool list_out = A.work_out != nullptr;
+    const bool count_done = A.cam_done != nullptr;
+
+    bool active = false;
+    int64_t id = 0;
+    State<double> x{};   // always a sum hi + lo of two floats
+    StepConst<double, Spin<double>> K;
+    double rcap = 0.0;
+    int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
+    bool hit = false;
+    StopBook &book = W.book;
+    unsigned long long &iters = W.iters;
+
+    for (;;) {
+        const uint64_t idle = ballot(!active);
+        if (idle) {
+            const unsigned done = __hip_atomic_load(&Q.float_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const unsigned h = __builtin_amdgcn_readfirstlane(lds_load(&Q.head));
+            const unsigned t = __builtin_amdgcn_readfirstlane(lds_load(&Q.tail));
+            // slots h, h + 1, ... that are published, as many as lanes are idle
+            const bool rdy = lane < t - h && lds_load(&Q.ready[(h + lane) % kHandCap]) != 0u;
+            const uint64_t rm = ballot(rdy);
+            unsigned c = (unsigned)__ffsll((long long)~rm) - 1u;   // published prefix
+            c = c < (unsigned)__popcll(idle) ? c : (unsigned)__popcll(idle);
+            if (c > 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const unsigned rank = lane_rank(idle);
+                const bool took = !active && rank < c;
+                if (took) {
+                    const unsigned s = (h + rank) % kHandCap;
+                    id = Q.id[s];
+                    nsteps = Q.nsteps[s];
+                    ncall = Q.ncall[s];
+                    ne = Q.ne[s];
+                    nr = Q.nr[s];
+                    n64 = Q.n64[s];
+                    hit = Q.hit[s] != 0;
+                    double *xp = &x.t;
+                    for (int k = 0; k < 8; ++k) xp[k] = (double)Q.hi[k][s] + (double)Q.lo[k][s];
+                    const DevCam cm = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
+                    K.B = make_spin(cm.a);
+                    K.rbh = cm.rbh;
+                    K.step_frac = A.step_frac;
+                    K.xi_eps = A.xi_eps;
+                    K.euler_inv = A.euler_inv;
+                    rcap = cm.rcap;
+                    active = true;
+                }
+                // every read of the taken slots is done before they are freed
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (took) lds_store(&Q.ready[(h + rank) % kHandCap], 0u);
+                if (lane == 0) lds_store(&Q.head, h + c);
+            } else if (idle == ~0ull) {
+                if (done == nfloat_waves && h == t) return true;
+                if (!W.exhausted) return false;
+                __builtin_amdgcn_s_sleep(2);
+                continue;
+            }
+        }
+
+        bool stop_now = false, keep = false;
+        iters += ballot(active) != 0ull;
+        if (active) {
+            auto record_disk_event = [&](double pth, double pr, double pph, const State<double> &x) {
+                const bool cross = record_disk && !hit && (pth - kHalfPi) * (x.th - kHalfPi) < 0.0;
+                if (record_disk && __builtin_expect(any_lane(cross), 0) && cross) {
+                    const double f = (kHalfPi - pth) / (x.th - pth);
+                    const double rc = pr + f * (x.r - pr);
+                    const DevCam &cw = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
+                    if (rc >= cw.disk_rmin && rc <= cw.disk_rmax) {
+                        double E, Lz, Qc, sx, cx;
+                        sin_cos<false>(x.th, sx, cx);
+                        conserved_sc(K.B.a, x, sx, cx, E, Lz, Qc);
+                        Column<double> D(GRAY_ARG(disk), A.stride, id);
+                        D.put(rc);
+                        D.next();
+                        D.put(pph + f * (x.ph - pph));
+                        D.next();
+                        D.put(disk_redshift(K.B.a, rc, E, Lz));
+                        hit = true;
+                    }
+                }
+            };
+            auto record = [&](const State<double> &xp, const State<double> &x) {
+                record_disk_event(xp.th, xp.r, xp.ph, x);
+                const double rmark = K.rbh + K.rbh;
+                const bool inward = xp.r >= rmark && x.r < rmark;
+                if (record_mark && __builtin_expect(any_lane(inward), 0) && inward) {
+                    const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
+                    Column<double> M(GRAY_ARG(mark), A.stride, id);
+                    for (int k = 0; k < 8; ++k) {
+                        M.put(v[k]);
+                        if (k < 7) M.next();
+                    }
+                }
+            };
+            double s64, c64;
+            sin_cos<true>(x.th, s64, c64);
+            const int fl = rk4_step<kPoleMonitor, true>(K, x, s64, c64, record);
+            if (fl >= 0) {
+                x = pair_rounded(x);
+                ++n64;
+            }
+            const State<double> &xr = x;
+            int32_t st = GRAY_RUNNING;
+            st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
+            st = (xr.r > A.r_escape && xr.kr > 0.0) ? GRAY_ESCAPED : st;
+            st = xr.r < rcap ? GRAY_CAPTURED : st;
+            st = (fl < 0 || !finite_state(xr)) ? GRAY_NONFINITE : st;
+            const bool ok = fl >= 0;
+            nsteps += ok;
+            ncall += ok;
+            ne += ok ? (fl & 1) : 0;
+            nr += ok ? ((fl >> 1) & 1) : 0;
+            const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
+            if (__builtin_expect(any_lane(stop), 0) && stop) {
+                Lane<GRAY_FP32C> P;
+                P.split(x);
+                c32_store(P, id, st, nsteps, ne, nr, n64, A.stride);
+                stop_now = true;
+                keep = st == GRAY_RUNNING;
+                active = false;
+            }
+        }
+        book.account(stop_now, keep, id, lane, list_out, count_done);
+    }
+}
+
+// Three waves per SIMD (at most 168 vector registers): the FP64 loop alone
+// would take 174, and the few it gives up are spilled on the recorder's
+// event path only.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate_c32(IntArgs A)
+{
+    __shared__ HandQueue Q;
+    constexpr unsigned kWaves = kBlock / kWave;
+    if (threadIdx.x < (unsigned)kHandCap) Q.ready[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        Q.head = 0u;
+        Q.tail = 0u;
+        Q.float_done = 0u;
+    }
+    __syncthreads();
+    const unsigned lane = threadIdx.x & (kWave - 1);
+    WaveCtx W;
+    if (threadIdx.x / kWave == kWaves - 1) {
+        while (!c32_fp64_phase(A, Q, kWaves - 1, W)) c32_float_phase<true>(A, Q, kWaves - 1, W);
+        W.book.finish(lane, A.work_out != nullptr, W.iters);
+    } else {
+        c32_float_phase<false>(A, Q, kWaves - 1, W);
     }
 }
 
@@ -1195,7 +1740,7 @@ static int device_info(DeviceInfo &out)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
         const void *kernels[kVariants] = {
-            (const void *)k_integrate<GRAY_FP64, kPoleMonitor>, (const void *)k_integrate<GRAY_FP32C, kPoleMonitor>,
+            (const void *)k_integrate<GRAY_FP64, kPoleMonitor>, (const void *)k_integrate_c32,
             (const void *)k_integrate<GRAY_FP64, kPoleEulerCrossing>, (const void *)k_integrate<GRAY_FP64, kPoleNone>,
             (const void *)k_integrate<GRAY_FP64, kPoleMonitor, GRAY_METRIC_DEFORMED>};
         for (int v = 0; v < kVariants; ++v) {
@@ -1441,7 +1986,7 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     const unsigned grid = (unsigned)(need < resident ? need : resident);
     switch (variant) {
     case 0: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
-    case 1: hipLaunchKernelGGL((k_integrate<GRAY_FP32C, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 1: hipLaunchKernelGGL(k_integrate_c32, dim3(grid), dim3(kBlock), 0, st, A); break;
     case 2: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleEulerCrossing>), dim3(grid), dim3(kBlock), 0, st, A); break;
     case 3: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
     default:
@@ -1460,7 +2005,10 @@ static int validate_integrate(const gray_camera *cams, int32_t ncam, const gray_
     if ((e = validate_state(s, p))) return e;
     if (s->n == 0) return GRAY_OK;
     if ((e = validate_cameras(cams, ncam, s->n, p->flags))) return e;
-    return call_metric(cams, ncam, p, metric);
+    if ((e = call_metric(cams, ncam, p, metric))) return e;
+    // FP32C keeps its FP64-step count per photon: a photon that has taken
+    // FP64 steps continues in FP64, also in a later call
+    return p->precision == GRAY_FP32C && !s->counters ? GRAY_EINVAL : GRAY_OK;
 }
 
 extern "C" int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p, gray_state *s,

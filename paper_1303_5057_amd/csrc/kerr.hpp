@@ -745,8 +745,8 @@ GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<floa
     // stages on non-finite values and is rejected here)
     sin_cos(nh.th, sy, cy);
     const bool reject = hbad || !(nh.th >= 0.0f && nh.th <= float(kPi)) ||
-                        !(isfinite(nh.t) && isfinite(nh.r) && isfinite(nh.ph) && isfinite(nh.kt) &&
-                          isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph)) ||
+                        !(__builtin_isfinite(nh.t) && __builtin_isfinite(nh.r) && __builtin_isfinite(nh.ph) && __builtin_isfinite(nh.kt) &&
+                          __builtin_isfinite(nh.kr) && __builtin_isfinite(nh.kth) && __builtin_isfinite(nh.kph)) ||
                         xi_violated_at(K.B.a, K.B.a2, nh.r, sy, cy, nh.kt, nh.kr, nh.kth, nh.kph, guard);
     if (__builtin_expect(any_lane(reject), 0))
         if (reject) return -2;
@@ -881,8 +881,8 @@ GRAY_HD int rk4_step_f32(const StepConst<float> &K, const FloatHorizon &H, State
     const int vm = xi_violated_guarded(K.B.a, K.B.a2, nh.r, ndr * (nh.r - H.rm), sy, cy, nh.kt, nh.kr, nh.kth,
                                        nh.kph, K.xi_eps);
     // a decision float cannot take is left to the FP64 step (state kept)
-    const bool undecided = vm < 0 || !(isfinite(nh.t) && isfinite(nh.r) && isfinite(nh.th) && isfinite(nh.ph) &&
-                                       isfinite(nh.kt) && isfinite(nh.kr) && isfinite(nh.kth) && isfinite(nh.kph));
+    const bool undecided = vm < 0 || !(__builtin_isfinite(nh.t) && __builtin_isfinite(nh.r) && __builtin_isfinite(nh.th) && __builtin_isfinite(nh.ph) &&
+                                       __builtin_isfinite(nh.kt) && __builtin_isfinite(nh.kr) && __builtin_isfinite(nh.kth) && __builtin_isfinite(nh.kph));
     if (__builtin_expect(any_lane(undecided), 0))
         if (undecided) return -2;
     const bool viol = vm > 0;

@@ -130,9 +130,12 @@ class Server:
         self.work = [torch.zeros(S + G.GRAY_WORKLIST_SLACK, dtype=torch.int32, device=dev)
                      for _ in range(2)]
         self.work_count = torch.zeros(2, dtype=torch.int32, device=dev)
-        # photons of each slot that have stopped (updated by the integrator)
+        # photons of each slot that have stopped (updated by the integrator),
+        # copied to one of two host buffers after each iteration: the loop
+        # reads iteration k's copy while iteration k + 1 runs
         self.cam_done = torch.zeros(self.max_slots, dtype=torch.int32, device=dev)
-        self.done_host = torch.zeros(self.max_slots, dtype=torch.int32, pin_memory=True)
+        self.done_host = [torch.zeros(self.max_slots, dtype=torch.int32, pin_memory=True) for _ in range(2)]
+        self.done_event = [torch.cuda.Event() for _ in range(2)]
         self.state = G.gray_state(self.x.data_ptr(), None if fp64 else self.lo.data_ptr(),
                                   self.status.data_ptr(), self.steps.data_ptr(), self.cam.data_ptr(),
                                   self.counters.data_ptr(), None, None, S, S)
@@ -157,6 +160,7 @@ class Server:
         self.max_active = 0
         self.max_used = 0
         self.admit_order: List[int] = []
+        self._gather: List[tuple] = []
 
     def _bind_work(self) -> None:
         """work_in = list `_cur` (read by the next integrate, appended to by
@@ -184,48 +188,72 @@ class Server:
         self.slots[k] = G.camera_struct(c, first)
         G.gray_camera_init_slot(self.slots, self.max_slots, k, self.p, self.state, self.stream)
         res = RequestResult(req.rid, req.arrival_s, admit_s=now, photons=n)
-        self.active[k] = (req, first, n, res)
+        # the first launch that includes the request
+        self.active[k] = (req, first, n, res, self.iterations)
         self.admit_order.append(req.rid)
         self.max_active = max(self.max_active, len(self.active))
         self.max_used = max(self.max_used, self.alloc.used())
         return True
 
     def _retire(self, k: int, now: float) -> RequestResult:
-        req, first, n, res = self.active.pop(k)
+        """Free slot k; the request's results are gathered on the device in
+        stream order (behind the launch still running) and read back once
+        the loop ends, so retiring never waits for the GPU."""
+        req, first, n, res, _ = self.active.pop(k)
         torch = self.torch
         st = self.steps[first:first + n]
-        res.photon_steps = int(st.to(torch.int64).sum().item())
+        dev = {"photon_steps": st.to(torch.int64).sum()}
         if self.keep_results:
-            res.status = self.status[first:first + n].cpu().numpy()
-            res.steps = st.cpu().numpy()
+            dev["status"] = self.status[first:first + n].clone()
+            dev["steps"] = st.clone()
             rows = self.x.view(8, self.capacity)[:, first:first + n].double()
             if self.lo is not None:
                 rows = rows + self.lo.view(8, self.capacity)[:, first:first + n].double()
-            res.x = rows.cpu().numpy()
+            dev["x"] = rows.clone()   # FP64: .double() is the pool itself
+        self._gather.append((res, dev))
         # free the range: its photons stay terminal (status is not RUNNING)
         self.alloc.release(first, n)
         self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0.0)
         res.done_s = now
         return res
 
-    def _iterate(self) -> float:
-        """One integrate launch over every in-flight request, then per-slot
-        status counts. Returns the wall time of the iteration in ms."""
-        torch = self.torch
-        t0 = time.perf_counter()
+    def _read_back(self) -> None:
+        """Host copies of the retired requests' device results."""
+        for res, dev in self._gather:
+            res.photon_steps = int(dev["photon_steps"].item())
+            if "x" in dev:
+                res.status = dev["status"].cpu().numpy()
+                res.steps = dev["steps"].cpu().numpy()
+                res.x = dev["x"].cpu().numpy()
+        self._gather = []
+
+    def _launch(self) -> int:
+        """Enqueue one integrate launch over every in-flight request and the
+        copy of the per-slot stop counts behind it; returns the buffer index
+        of that copy. Nothing waits here."""
+        b = self.iterations % 2
         self.p.call_steps = int(self.call_steps)
         G.gray_integrate(self.slots, self.max_slots, self.p, self.state, self.ws_ptr, self.ws_bytes,
                          self.stream)
         self._cur = 1 - self._cur          # the ids still running are the next input
         self._bind_work()
         self.iterations += 1
-        self.done_host.copy_(self.cam_done, non_blocking=True)
-        torch.cuda.current_stream().synchronize()
-        dt = (time.perf_counter() - t0) * 1e3
-        # aim the next iteration at slice_ms
-        scale = self.slice_ms / max(dt, 1e-3)
-        self.call_steps = int(min(4096, max(32, self.call_steps * min(4.0, max(0.25, scale)))))
-        return dt
+        self.done_host[b].copy_(self.cam_done, non_blocking=True)
+        self.done_event[b].record()
+        return b
+
+    def _wait(self, b: int, prev_done: Optional[float]) -> tuple:
+        """Wait for the launch whose counts went to buffer b; adapt the step
+        budget to the time since the previous launch was seen to end (the
+        iteration time, the loop keeping the GPU busy). Returns the counts
+        and the time this launch was seen to end."""
+        self.done_event[b].synchronize()
+        t = time.perf_counter()
+        if prev_done is not None:
+            dt = (t - prev_done) * 1e3
+            scale = self.slice_ms / max(dt, 1e-3)
+            self.call_steps = int(min(4096, max(32, self.call_steps * min(4.0, max(0.25, scale)))))
+        return self.done_host[b].numpy().copy(), t
 
     # -------------------------------------------------------------- driver
     def run(self, requests: Sequence[Request], realtime: bool = True,
@@ -237,6 +265,9 @@ class Server:
         done: List[RequestResult] = []
         t_start = time.perf_counter()
         i = 0
+        # (count buffer, launch index) of the launch not yet read back
+        inflight: Optional[tuple] = None
+        last_done: Optional[float] = None
         while i < len(pending) or waiting or self.active:
             now = time.perf_counter() - t_start
             while i < len(pending) and (not realtime or pending[i].arrival_s <= now):
@@ -248,16 +279,43 @@ class Server:
                 if i < len(pending):
                     time.sleep(max(0.0, pending[i].arrival_s - (time.perf_counter() - t_start)))
                 continue
-            self._iterate()
+            # Launch the next iteration before reading the previous one's
+            # counts, so the GPU runs while the host retires and admits
+            # (stream order keeps every admission behind the running launch).
+            b = self._launch()
+            prev, inflight = inflight, (b, self.iterations - 1)
+            if prev is None:
+                continue
+            counts, last_done = self._wait(prev[0], last_done)
             now = time.perf_counter() - t_start
-            done_counts = self.done_host.numpy()
+            # a slot's count in that copy is its request's only if the
+            # request was in that launch (a reused slot still shows the
+            # previous request's count until its own init runs)
             for k in list(self.active.keys()):
-                if done_counts[k] == self.active[k][2]:
+                if self.active[k][4] <= prev[1] and counts[k] == self.active[k][2]:
                     r = self._retire(k, now)
                     done.append(r)
                     if on_done:
                         on_done(r)
+            if not self.active:
+                # nothing left to run: the launch behind is empty for us
+                self.torch.cuda.current_stream().synchronize()
+                inflight = None
+                last_done = None
+        self.torch.cuda.current_stream().synchronize()
+        self._read_back()
         return done
+
+
+# request-size classes for latency breakdowns: photons <= 128^2, <= 512^2, more
+SIZE_CLASSES = (("small", 0, 128 * 128), ("medium", 128 * 128, 512 * 512), ("large", 512 * 512, 1 << 62))
+
+
+def size_class(photons: int) -> str:
+    for name, lo, hi in SIZE_CLASSES:
+        if lo < photons <= hi:
+            return name
+    return SIZE_CLASSES[0][0]
 
 
 def latency_stats(results: Sequence[RequestResult], skip: int = 0) -> dict:
@@ -265,7 +323,18 @@ def latency_stats(results: Sequence[RequestResult], skip: int = 0) -> dict:
     lat = np.array([r.latency_s for r in rs]) * 1e3
     steps = sum(r.photon_steps for r in rs)
     span = max(r.done_s for r in rs) - min(r.arrival_s for r in rs)
-    return {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-            "photon_steps_per_s": steps / span, "span_s": span,
-            "photons": int(sum(r.photons for r in rs))}
+    out = {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+           "photon_steps_per_s": steps / span, "span_s": span,
+           "photons": int(sum(r.photons for r in rs))}
+    by = {}
+    for name, _, _ in SIZE_CLASSES:
+        sel = np.array([size_class(r.photons) == name for r in rs])
+        if sel.any():
+            w = np.array([(r.admit_s - r.arrival_s) for r in rs])[sel] * 1e3
+            by[name] = {"requests": int(sel.sum()), "p50_ms": float(np.percentile(lat[sel], 50)),
+                        "p99_ms": float(np.percentile(lat[sel], 99)),
+                        "queue_wait_p50_ms": float(np.percentile(w, 50)),
+                        "queue_wait_p99_ms": float(np.percentile(w, 99))}
+    out["by_size"] = by
+    return out

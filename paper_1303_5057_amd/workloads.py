@@ -64,12 +64,12 @@ class Params:
     call_steps: int = 0
     precision: str = "fp64"      # "fp64" or "fp32c"
     record_disk: bool = False
-    # FP32C: double-precision steps near the horizon, the poles and radial
-    # turning points (r < r_bh (1 + fp64_horizon), sin(theta) < fp64_pole,
-    # |k^r| < fp64_turn |k^t|).
-    fp64_horizon: float = 1.0
+    # FP32C: a photon continues in double precision once it comes near the
+    # horizon, a pole or a radial turning point (r < r_bh (1 + fp64_horizon),
+    # sin(theta) < fp64_pole, |k^r| < fp64_turn |k^t|).
+    fp64_horizon: float = 0.02
     fp64_pole: float = 0.05
-    fp64_turn: float = 0.01
+    fp64_turn: float = 0.0
     # treatment of the polar axis (Sec. 2): 0 the production null-condition
     # monitor, 1 the earlier Euler step on pole crossings, 2 none
     pole_mode: int = 0

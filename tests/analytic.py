@@ -88,6 +88,24 @@ def effective_impact(a, incl, E, L, Q):
     return alpha, beta
 
 
+def polar_turning_sin(a, E, L, Q):
+    """sin(theta) at the polar turning point of a Kerr null geodesic: the
+    smallest sin(theta) its path reaches. The polar potential
+    Theta(theta) = Q - cos^2 (L^2 / sin^2 - a^2 E^2) vanishes there; with
+    u = cos^2 it reads a^2 E^2 u^2 + (Q + L^2 - a^2 E^2) u - Q = 0 (times
+    -(1 - u)), whose root in [0, 1] is the largest cos^2 reached."""
+    E, L, Q = np.asarray(E, float), np.asarray(L, float), np.asarray(Q, float)
+    b = Q + L * L - a * a * E * E
+    if a == 0.0:
+        u = Q / (Q + L * L)
+    else:
+        A = a * a * E * E
+        # the root -b/2A + sqrt(b^2 + 4AQ)/2A without cancellation for b > 0
+        disc = np.sqrt(b * b + 4.0 * A * Q)
+        u = np.where(b > 0, 2.0 * Q / (b + disc), (disc - b) / (2.0 * A))
+    return np.sqrt(np.clip(1.0 - u, 0.0, 1.0))
+
+
 class CriticalBand:
     """Distance from a ray's effective image-plane point to the critical curve."""
 

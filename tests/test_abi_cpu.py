@@ -130,6 +130,16 @@ def test_invalid_state_rejected(lib):
     assert G.load().gray_camera_init(arr, 2, ctypes.byref(p), ctypes.byref(s), None) == G.GRAY_EINVAL
 
 
+def test_fp32c_integrate_needs_counters(lib):
+    """FP32C keeps each photon's FP64-step count (a photon that has taken FP64
+    steps continues in FP64), so its integrate call requires the counters."""
+    p = G.params_struct(W.Params(precision="fp32c"))
+    s = _state(64, 64, lo=0x9000)
+    assert _call_integrate([CAM], p, s) == G.GRAY_EINVAL
+    s.counters = 0xA000
+    assert _call_integrate([CAM], p, s, ws=None) == G.GRAY_EWORKSPACE
+
+
 def test_fp32c_supports_only_the_production_pole_treatment(lib):
     p = G.params_struct(W.Params(precision="fp32c", pole_mode=G.GRAY_POLE_NONE))
     s = _state(64, 64, lo=0x9000)
