@@ -381,6 +381,8 @@ struct IntArgs {
     uint32_t flags;
     int32_t refill;
     int32_t two_ended;          // odd wave slots take ids from the end of the queue
+    int32_t helper;             // FP32C: the FP64 wave may run float photons
+    int32_t pad;
 };
 
 // Argument block fields of the running k_integrate, read again where they
@@ -947,6 +949,7 @@ constexpr unsigned kFloatQuota = 64;     // slots the float waves may fill; the
                                          // hand-offs, so it never waits
 constexpr unsigned kHelperLimit = 1;     // photons waiting, from which on the
                                          // FP64 wave takes no float work
+constexpr int64_t kHelperPhotonsPerLane = 4;
 
 struct HandQueue {
     unsigned head;        // slots taken by the FP64 wave (monotonic)
@@ -1343,7 +1346,7 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
                 if (lane == 0) lds_store(&Q.head, h + c);
             } else if (idle == ~0ull) {
                 if (done == nfloat_waves && h == t) return true;
-                if (!W.exhausted) return false;
+                if (!W.exhausted && A.helper) return false;
                 __builtin_amdgcn_s_sleep(2);
                 continue;
             }
@@ -1434,7 +1437,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const unsigned lane = threadIdx.x & (kWave - 1);
     WaveCtx W;
     if (threadIdx.x / kWave == kWaves - 1) {
-        while (!c32_fp64_phase(A, Q, kWaves - 1, W)) c32_float_phase<true>(A, Q, kWaves - 1, W);
+        while (!c32_fp64_phase(A, Q, kWaves - 1, W) && A.helper) c32_float_phase<true>(A, Q, kWaves - 1, W);
         W.book.finish(lane, A.work_out != nullptr, W.iters);
     } else {
         c32_float_phase<false>(A, Q, kWaves - 1, W);
@@ -1980,6 +1983,12 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     A.refill = 1;
     const int variant = variant_of(p, metric);
     const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[variant];
+    // FP32C: the FP64 wave of a block runs float photons while none waits
+    // for it only when the launch is bound by throughput (work lists, or at
+    // least kHelperPhotonsPerLane photons per float lane); a launch bound by
+    // its longest photons keeps it free, so that a long photon that goes
+    // over to FP64 is taken at once.
+    A.helper = wl || s->n >= kHelperPhotonsPerLane * resident * (kBlock - kWave);
     // In work-list mode the list length is only known on the device; the grid
     // is capped at kMaxListWaves waves, which bounds the unused list tail.
     const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave)) : blocks_for(s->n);
