@@ -102,7 +102,7 @@ def lib():
             "oracle_conserved_jp": (None, [d, d, _D, _D]),
             "oracle_trace": (ctypes.c_int, [P, d, _D, _I, _I, _I, _D]),
             "oracle_trace_path": (ctypes.c_int, [P, d, _D, i32, _D, _I, _I]),
-            "oracle_run": (None, [P, i64, _D, _D, _I, _I, _I, _I, _D, i32]),
+            "oracle_run": (None, [P, i64, _D, _D, _I, _I, _I, _I, _D, _D, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -287,9 +287,11 @@ class RunResult:
     n_euler: np.ndarray
     n_remap: np.ndarray
     disk: np.ndarray | None
+    mark: np.ndarray | None = None   # (n, 8): last state with r >= 2 r_bh before the last fall below
 
 
-def run(params: Params, a, x0, nthreads: int = 0, want_disk: bool = False) -> RunResult:
+def run(params: Params, a, x0, nthreads: int = 0, want_disk: bool = False,
+        want_mark: bool = False) -> RunResult:
     """Trace every photon of x0 (shape (n, 8)); a is a scalar or per-photon array."""
     x = np.array(x0, dtype=np.float64, order="C").reshape(-1, 8)
     n = x.shape[0]
@@ -299,9 +301,11 @@ def run(params: Params, a, x0, nthreads: int = 0, want_disk: bool = False) -> Ru
     ne = np.zeros(n, dtype=np.int32)
     nr = np.zeros(n, dtype=np.int32)
     disk = np.zeros((n, 3)) if want_disk else None
+    mark = np.zeros((n, 8)) if want_mark else None
     lib().oracle_run(ctypes.byref(params), n, _dp(av), _dp(x), _ip(status), _ip(steps), _ip(ne),
-                     _ip(nr), _dp(disk) if disk is not None else None, int(nthreads))
-    return RunResult(status, x, steps, ne, nr, disk)
+                     _ip(nr), _dp(disk) if disk is not None else None,
+                     _dp(mark) if mark is not None else None, int(nthreads))
+    return RunResult(status, x, steps, ne, nr, disk, mark)
 
 
 def drift(E0, L0, Q0, E, L, Q):

@@ -531,15 +531,20 @@ static int disk_crossing(double a, double rmin, double rmax, const double *xp, c
 
 /* Integrate one photon from its current state until it is captured, escapes,
  * turns non-finite or reaches max_steps. The state x is the last accepted
- * state on return. */
-int oracle_trace(const oracle_params *p, double a, double x[8], int32_t *steps,
-                 int32_t *n_euler, int32_t *n_remap, double disk[3])
+ * state on return. mark (optional) receives the last accepted state with
+ * r >= 2 r_bh before the photon last fell below 2 r_bh (all zero if it never
+ * did): where a captured photon's state is compared, since its components
+ * in Boyer-Lindquist coordinates diverge at the horizon. */
+int oracle_trace_mark(const oracle_params *p, double a, double x[8], int32_t *steps,
+                      int32_t *n_euler, int32_t *n_remap, double disk[3], double mark[8])
 {
     double rcap = oracle_horizon(a) * (1.0 + p->horizon_eps);
+    double rmark = 2.0 * oracle_horizon(a);
     double rmin = p->disk_rmin < 0.0 ? oracle_r_isco(a) : p->disk_rmin;
     int32_t s = 0, ne = 0, nr = 0;
     int hit = 0;
     if (disk) disk[0] = disk[1] = disk[2] = 0.0;
+    if (mark) memset(mark, 0, 8 * sizeof(double));
 
     int status = ORACLE_RUNNING;
     while (status == ORACLE_RUNNING) {
@@ -554,12 +559,19 @@ int oracle_trace(const oracle_params *p, double a, double x[8], int32_t *steps,
         nr += (fl >> 1) & 1;
         ++s;
         if (p->record_disk && disk && !hit) hit = disk_crossing(a, rmin, p->disk_rmax, xp, x, disk);
+        if (mark && xp[1] >= rmark && x[1] < rmark) memcpy(mark, xp, 8 * sizeof(double));
         status = classify_after_step(p, rcap, x, s);
     }
     if (steps) *steps = s;
     if (n_euler) *n_euler = ne;
     if (n_remap) *n_remap = nr;
     return status;
+}
+
+int oracle_trace(const oracle_params *p, double a, double x[8], int32_t *steps,
+                 int32_t *n_euler, int32_t *n_remap, double disk[3])
+{
+    return oracle_trace_mark(p, a, x, steps, n_euler, n_remap, disk, NULL);
 }
 
 /* Same loop, recording every accepted state (path[i*8..]) and the step's
@@ -591,7 +603,7 @@ int oracle_trace_path(const oracle_params *p, double a, double x[8], int32_t max
  * overwrites x. OpenMP over photons; they never interact (Sec. 1, Sec. 2). */
 void oracle_run(const oracle_params *p, int64_t n, const double *a, double *x,
                 int32_t *status, int32_t *steps, int32_t *n_euler, int32_t *n_remap,
-                double *disk, int32_t nthreads)
+                double *disk, double *mark, int32_t nthreads)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -601,7 +613,8 @@ void oracle_run(const oracle_params *p, int64_t n, const double *a, double *x,
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i) {
         int32_t s, ne, nr;
-        status[i] = oracle_trace(p, a[i], x + i * 8, &s, &ne, &nr, disk ? disk + i * 3 : NULL);
+        status[i] = oracle_trace_mark(p, a[i], x + i * 8, &s, &ne, &nr, disk ? disk + i * 3 : NULL,
+                                      mark ? mark + i * 8 : NULL);
         steps[i] = s;
         if (n_euler) n_euler[i] = ne;
         if (n_remap) n_remap[i] = nr;

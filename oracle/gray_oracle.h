@@ -90,11 +90,13 @@ double oracle_disk_redshift(double a, double rc, double E, double L);
 /* Whole trajectories. */
 int oracle_trace(const oracle_params *p, double a, double x[8], int32_t *steps,
                  int32_t *n_euler, int32_t *n_remap, double disk[3]);
+int oracle_trace_mark(const oracle_params *p, double a, double x[8], int32_t *steps,
+                      int32_t *n_euler, int32_t *n_remap, double disk[3], double mark[8]);
 int oracle_trace_path(const oracle_params *p, double a, double x[8], int32_t max_pts,
                       double *path, int32_t *flags, int32_t *n_pts);
 void oracle_run(const oracle_params *p, int64_t n, const double *a, double *x,
                 int32_t *status, int32_t *steps, int32_t *n_euler, int32_t *n_remap,
-                double *disk, int32_t nthreads);
+                double *disk, double *mark, int32_t nthreads);
 
 #ifdef __cplusplus
 }

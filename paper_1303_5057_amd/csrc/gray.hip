@@ -950,6 +950,12 @@ constexpr unsigned kFloatQuota = 64;     // slots the float waves may fill; the
 constexpr unsigned kHelperLimit = 1;     // photons waiting, from which on the
                                          // FP64 wave takes no float work
 constexpr int64_t kHelperPhotonsPerLane = 4;
+// The FP64 wave in its float phase is the queue's only consumer and must
+// never wait for a slot: it takes float work only while no slot is taken,
+// so afterwards it adds at most kWave photons to the at most kFloatQuota
+// the float waves may add.
+static_assert(kHandCap >= (int)kFloatQuota + kWave, "the FP64 wave's own hand-offs always fit");
+static_assert(kHelperLimit == 1, "the bound above assumes the helper refills only with no slot taken");
 
 struct HandQueue {
     unsigned head;        // slots taken by the FP64 wave (monotonic)

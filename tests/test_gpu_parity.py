@@ -19,14 +19,23 @@ pytestmark = pytest.mark.gpu
 
 PRECS = ["fp64", "fp32c"]
 STEP_MISMATCH = {"fp64": 1e-3, "fp32c": 2e-3}
+FLIPS = {"fp64": 0.0, "fp32c": 1e-3}       # fallback decisions that flipped
+# rays left out of state comparison: all, and the escaped ones among them
+EXCLUDED = {"fp64": 0.0, "fp32c": 0.25}
+EXCLUDED_ESCAPED = {"fp64": 0.0, "fp32c": 0.04}
 
 
-def _check(rep, prec, allow=None):
+def _check(rep, prec, allow=None, excluded=None):
     print(prec, rep, flush=True)
     assert rep.flag_mismatch == 0
     assert rep.state_bad == 0
     assert rep.counter_bad == 0
     assert rep.step_mismatch <= (STEP_MISMATCH[prec] if allow is None else allow) * rep.n
+    assert rep.flips <= FLIPS[prec] * rep.n + (1 if prec == "fp32c" else 0)
+    if rep.n >= 100:
+        tot, esc = (EXCLUDED[prec], EXCLUDED_ESCAPED[prec]) if excluded is None else excluded
+        assert rep.excluded <= tot
+        assert rep.excluded_escaped <= esc
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -34,7 +43,7 @@ def test_c1_schwarzschild_full_grid(prec):
     cam, p = W.C1, W.Params(precision=prec)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
-    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec), prec)
+    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec, g.mark.T), prec)
     assert np.array_equal(g.flag, g.status)
     # independent of the oracle: the sqrt(27) shadow on the pixel grid
     al, be = np.meshgrid(-10 + 20 * (np.arange(64) + 0.5) / 64, -10 + 20 * (np.arange(64) + 0.5) / 64)
@@ -53,7 +62,7 @@ def test_c2_kerr_ragged_grid(prec):
     cam, p = W.scaled(W.C2, 97, 95), W.Params(precision=prec)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
-    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec), prec)
+    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec, g.mark.T), prec)
     assert set(np.unique(g.status)) == {G.CAPTURED, G.ESCAPED}
 
 
@@ -65,7 +74,7 @@ def test_c2_full_size_sampled(prec):
     g = run_gpu([cam], p)
     ids = W.subsample_ids(cam, 8)
     o = run_oracle(cam, p, ids)
-    _check(compare_prec(g.status[ids], g.steps[ids], g.x.T[ids], g.counters[:, ids], o, prec), prec)
+    _check(compare_prec(g.status[ids], g.steps[ids], g.x.T[ids], g.counters[:, ids], o, prec, g.mark.T[ids]), prec)
     assert np.all((g.status == G.CAPTURED) | (g.status == G.ESCAPED))
 
 
@@ -79,7 +88,7 @@ def test_many_cameras_one_launch(prec):
     for k, cam in enumerate(cams):
         sl = slice(g.offsets[k], g.offsets[k + 1])
         o = run_oracle(cam, p)
-        _check(compare_prec(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, prec), prec,
+        _check(compare_prec(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, prec, g.mark.T[sl]), prec,
                allow=0.01)
         assert g.counts[k].tolist() == np.bincount(g.status[sl], minlength=5).tolist()
 
@@ -189,7 +198,7 @@ def test_single_photon_and_odd_shapes(prec):
     for k, cam in enumerate(cams):
         sl = slice(g.offsets[k], g.offsets[k + 1])
         o = run_oracle(cam, p)
-        _check(compare_prec(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, prec), prec, 0)
+        _check(compare_prec(g.status[sl], g.steps[sl], g.x.T[sl], g.counters[:, sl], o, prec, g.mark.T[sl]), prec, 0)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -278,15 +287,17 @@ def _stage_offsets(cam, p, ids):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_coarse_steps_exercise_full_stage_angles(prec):
-    """With Delta = 1/2 the theta offsets of the RK4 stages exceed the
-    small-angle series' range (1/16) on many steps, so the stages take the
-    full sin/cos there (a wave-wide branch in the kernels); the result still
-    matches the oracle under the usual rules."""
+    """With a coarse step (Delta = 1/2 in FP64, 1/4 in FP32C) the theta
+    offsets of the RK4 stages exceed the small-angle series' range (1/16) on
+    many steps, so the stages take the full sin/cos there (a wave-wide branch
+    in the kernels); the result still matches the oracle under the usual
+    rules. (In FP32C Delta = 1/2 would leave every ray Euler-locked, out of
+    state comparison; at 1/4 a third of them are.)"""
     cam = W.Camera(0.9, 1000.0, np.radians(60.0), 40, 36, -8.0, 8.0, -8.0, 8.0)
-    p = W.Params(precision=prec, step_frac=0.5)
+    p = W.Params(precision=prec, step_frac=0.5 if prec == "fp64" else 0.25)
     d = _stage_offsets(cam, p, [5, 300, 777, 1111])
     assert np.mean(d > 0.0625) > 0.05, np.mean(d > 0.0625)
     g = run_gpu([cam], p)
     o = run_oracle(cam, p)
-    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec), prec,
-           allow=2 * STEP_MISMATCH[prec])
+    _check(compare_prec(g.status, g.steps, g.x.T, g.counters, o, prec, g.mark.T), prec,
+           allow=2 * STEP_MISMATCH[prec], excluded=(0.4, 0.1))

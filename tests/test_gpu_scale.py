@@ -22,6 +22,8 @@ def _gather(b, res, ids):
     rows = lambda t, k: t.view(k, b.stride)[:, idx].cpu().numpy()
     out = {"status": rows(b.status, 1)[0], "steps": rows(b.steps, 1)[0],
            "x": rows(res.xf, 8).T, "counters": rows(b.counters, 3)}
+    if b.mark is not None:
+        out["mark"] = rows(b.mark, 8).T
     if b.disk is not None:
         out["disk"] = rows(b.disk, 3).T
     return out
@@ -75,6 +77,43 @@ def test_c4_sweep_one_launch_fp64_sampled():
     assert bad == 0
 
 
+def test_c4_sweep_one_launch_fp32c_sampled():
+    """The 256-camera sweep in FP32C, one persistent launch, against the
+    oracle on every 8th camera (1 ray in 97), under the FP32C rules: the
+    excluded fraction, step mismatches and flipped fallback decisions are
+    summed over the sample and bounded."""
+    import torch
+    cams = W.sweep_cameras()
+    p = W.Params(precision="fp32c")
+    b = G.Batch(cams, p)
+    res = b.run(cons=False)
+    torch.cuda.synchronize()
+    counts = res.counts.view(-1, 5).cpu().numpy()
+    assert counts[:, G.RUNNING].sum() == 0
+    first = np.cumsum([0] + [c.n for c in cams])
+    n = flag = state = steps = flips = 0
+    excluded = excluded_esc = 0.0
+    for k in range(0, 256, 8):
+        cam = cams[k]
+        local = np.arange(k % 97, cam.n, 97)
+        g = _gather(b, res, first[k] + local)
+        o = run_oracle(cam, p, local)
+        rep = compare(g["status"], g["steps"], g["x"], g["counters"], o, RTOL["fp32c"], STATE_BAND["fp32c"],
+                      skip_locked=True, g_mark=g["mark"])
+        n += rep.n
+        flag += rep.flag_mismatch
+        state += rep.state_bad
+        steps += rep.step_mismatch
+        flips += rep.flips
+        excluded += rep.excluded * rep.n
+        excluded_esc += rep.excluded_escaped * rep.n
+    print(f"FP32C sweep sample: rays {n} flag {flag} state {state} step mismatch {steps} flips {flips} "
+          f"excluded {excluded / n:.4f} (escaped {excluded_esc / n:.4f})", flush=True)
+    assert flag == 0 and state == 0
+    assert steps <= 2e-3 * n and flips <= 1e-3 * n
+    assert excluded / n <= 0.25 and excluded_esc / n <= 0.04
+
+
 def test_large_batch_every_photon_advances_once_per_call():
     """2^27 photons in one batch (134M: ids, launch-order entries and queue
     positions span 1/16 of their 32-bit range, grabs are 512 ids): with
@@ -95,3 +134,43 @@ def test_large_batch_every_photon_advances_once_per_call():
     assert res.counts.view(-1, 5).cpu().numpy()[0].tolist() == [b.n, 0, 0, 0, 0]
     del b, res
     torch.cuda.empty_cache()
+
+
+def test_c2_full_grid_fp32c_against_oracle():
+    """Every ray of the 512 x 512 edge-on grid in FP32C against the FP64
+    oracle, under the FP32C rules (tests/parity.py): flags exact outside the
+    1e-3 M band; states to 1e-3 where step counts and fallback decisions
+    agree, for rays outside the 2e-2 M band and not Euler-locked; the rays
+    with another step count or a flipped fallback decision, and the rays left
+    out, counted and bounded."""
+    import analytic
+    import torch
+    from parity import state_close
+    cam, p = W.C2, W.Params(precision="fp32c")
+    b = G.Batch([cam], p)
+    res = b.run()
+    torch.cuda.synchronize()
+    st, sp = b.rows(b.status, 1)[0], b.rows(b.steps, 1)[0]
+    x, ctr = b.rows(res.xf, 8).T, b.rows(b.counters, 3)
+    c0 = b.rows(res.cons, 9)[0:3]
+    o = run_oracle(cam, p)
+    mk = b.rows(b.mark, 8).T
+    rep = compare(st, sp, x, ctr, o, RTOL["fp32c"], STATE_BAND["fp32c"], skip_locked=True, g_mark=mk)
+    print(rep, flush=True)
+    # where the mismatches fall (diagnostics)
+    smin = analytic.polar_turning_sin(cam.a, c0[0], c0[1], c0[2])
+    at_mark = (o.status == G.CAPTURED) & (o.mark[:, 1] > 0)
+    ok, err = state_close(np.where(at_mark[:, None], mk, x), np.where(at_mark[:, None], o.mark, o.x), 1e-3)
+    same = (sp == o.steps) & (st == o.status)
+    flip = same & ((ctr[0] != o.n_euler) | (ctr[1] != o.n_remap))
+    cons = (o.band_dist > STATE_BAND["fp32c"]) & (o.n_euler <= 0.1 * o.steps)
+    e = np.where(same & cons & ~flip, err.max(axis=1), 0.0)
+    for i in np.argsort(-e)[:5]:
+        print(f"  worst compared ray {i}: err {e[i]:.2e} comp {err[i].argmax()} band {o.band_dist[i]:.3g} "
+              f"sin_min {smin[i]:.3f} FP64 steps {ctr[2][i]} of {sp[i]}", flush=True)
+    fl = np.nonzero(flip & cons)[0]
+    print("flipped rays: euler GPU/oracle", [(int(ctr[0][i]), int(o.n_euler[i])) for i in fl[:10]], flush=True)
+    assert rep.flag_mismatch == 0 and rep.state_bad == 0
+    assert rep.flips <= 1e-3 * rep.n
+    assert rep.step_mismatch <= 2e-3 * rep.n
+    assert rep.excluded <= 0.25 and rep.excluded_escaped <= 0.04

@@ -230,3 +230,29 @@ def test_printed_spins():
     a = 1 - 10 ** (-np.arange(16) / 5)
     for v in g["printed"]:
         assert np.min(np.abs(a - v)) < 5e-7
+
+
+def test_mark_is_last_state_outside_twice_horizon(orc):
+    """oracle.run's mark: the last accepted state with r >= 2 r_bh before the
+    photon last fell below 2 r_bh (zeros when it never did), checked against
+    the whole path of each ray."""
+    a = 0.7
+    rbh = orc.horizon(a)
+    g = np.random.Generator(np.random.PCG64(7))
+    al, be = g.uniform(-7.0, 7.0, 40), g.uniform(-7.0, 7.0, 40)
+    X0 = np.array([orc.camera(a, 1000.0, 1.1, x, y) for x, y in zip(al, be)])
+    p = orc.make_params()
+    res = orc.run(p, a, X0, want_mark=True)
+    captured = 0
+    for i in range(len(X0)):
+        st, path, fl = orc.trace_path(p, a, X0[i])
+        states = np.vstack([X0[i], path])
+        down = np.nonzero((states[:-1, 1] >= 2 * rbh) & (states[1:, 1] < 2 * rbh))[0]
+        if len(down):
+            assert np.array_equal(res.mark[i], states[down[-1]])
+        else:
+            assert not res.mark[i].any()
+        captured += st == orc.CAPTURED
+        if st == orc.CAPTURED:
+            assert len(down) and res.mark[i][1] >= 2 * rbh
+    assert 5 <= captured < len(X0)
