@@ -41,6 +41,8 @@ BAND = 1e-3
 # the largest RK4 truncation error of the scheme at Delta = 1/32; drift
 # statistics are also reported without them.
 AXIS_SIN = 0.02
+# FP32C state comparison leaves out rays this close (M) to the critical curve
+FP32C_STATE_BAND = 2e-2
 
 
 def measured_traffic(prec: str):
@@ -201,7 +203,7 @@ def cpu_baseline(cam, params, every: int):
                            euler_div=params.euler_div, max_steps=params.max_steps)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
-    res = oracle.run(p, cam.a, X0, nthreads=threads)
+    res = oracle.run(p, cam.a, X0, nthreads=threads, want_mark=True)
     dt = time.perf_counter() - t0
     nsteps = int(res.steps.sum())
     cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
@@ -228,7 +230,7 @@ def cpu_baseline(cam, params, every: int):
                "single_thread_64x64_schwarzschild_ns_per_photon_step": dt1 * 1e9 / int(r1.steps.sum()),
                "nproc": os.cpu_count(), "cpu_model": model}
     ref = {"ids": ids, "status": res.status, "steps": res.steps, "x": res.x, "euler": res.n_euler,
-           "band": band_distance(cam, cons0[:, 0], cons0[:, 1], cons0[:, 2])}
+           "mark": res.mark, "band": band_distance(cam, cons0[:, 0], cons0[:, 1], cons0[:, 2])}
     return summary, ref
 
 
@@ -250,10 +252,10 @@ def oracle_sample(cam, params, ids):
                            record_disk=params.record_disk, disk_rmin=params.disk_rmin,
                            disk_rmax=params.disk_rmax)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    res = oracle.run(p, cam.a, X0, nthreads=threads, want_disk=params.record_disk)
+    res = oracle.run(p, cam.a, X0, nthreads=threads, want_disk=params.record_disk, want_mark=True)
     cons0 = np.array([oracle.conserved(cam.a, x) for x in X0])
     return {"ids": ids, "status": res.status, "steps": res.steps, "x": res.x, "euler": res.n_euler,
-            "band": band_distance(cam, cons0[:, 0], cons0[:, 1], cons0[:, 2]), "disk": res.disk}
+            "mark": res.mark, "band": band_distance(cam, cons0[:, 0], cons0[:, 1], cons0[:, 2]), "disk": res.disk}
 
 
 def error_vs_oracle(np, g: dict, ref: dict, gathered: bool = False) -> dict:
@@ -261,32 +263,50 @@ def error_vs_oracle(np, g: dict, ref: dict, gathered: bool = False) -> dict:
 
     State error per ray: max over components of |x_gpu - x_ora| / (|x_ora| + f)
     with f = 1 for t, r, theta, phi, k^t, k^r and 1/r for k^theta, k^phi,
-    over rays whose outcome and step count agree, outside the 1e-3 M band.
-    Also the fraction of those rays whose step counts differ, the outcome
-    mismatches outside the band, and the rays the FP32C parity rule leaves out
-    of state comparison (within 1e-2 M of the critical curve, or more than 10%
-    Euler steps in the oracle)."""
+    over rays whose outcome and step count agree, outside the 1e-3 M band,
+    at the horizon stop ("state_err") and, for captured rays, at their mark
+    (the last state with r >= 2 r_bh, where the FP32C rule compares them).
+    Also the step-count mismatches, the flipped Euler-fallback decisions
+    (same step count, different count of fallbacks), the outcome mismatches
+    outside the band, and what the FP32C rule leaves out of state comparison
+    (within FP32C_STATE_BAND M of the critical curve, or more than 10% Euler
+    steps in the oracle)."""
     ids = np.arange(len(ref["ids"])) if gathered else ref["ids"]
     st, sp, x = g["status"][ids], g["steps"][ids], g["x"][ids]
     far = ref["band"] > BAND
     same = (st == ref["status"]) & (sp == ref["steps"])
-    r = np.abs(ref["x"][:, 1])
-    floor = np.stack([np.ones_like(r)] * 6 + [1.0 / r, 1.0 / r], axis=1)
-    err = (np.abs(x - ref["x"]) / (np.abs(ref["x"]) + floor)).max(axis=1)
-    sel = same & far
+
+    def rel(xg, xo):
+        r = np.abs(xo[:, 1])
+        floor = np.stack([np.ones_like(r)] * 6 + [1.0 / np.maximum(r, 1e-300)] * 2, axis=1)
+        return (np.abs(xg - xo) / (np.abs(xo) + floor)).max(axis=1)
+
+    err = rel(x, ref["x"])
+    flip = same & (g["euler"][ids] != ref["euler"])
+    at_mark = (ref["status"] == 1) & (ref["mark"][:, 1] > 0) if ref.get("mark") is not None else None
+    err_m = err.copy()
+    if at_mark is not None and g.get("mark") is not None:
+        err_m[at_mark] = rel(g["mark"][ids][at_mark], ref["mark"][at_mark])
+    sel = same & far & ~flip
     e = err[sel]
     locked = ref["euler"] > 0.1 * ref["steps"]
-    excluded = (ref["band"] <= 1e-2) | locked
+    excluded = (ref["band"] <= FP32C_STATE_BAND) | locked
     mism = (~same) & far
+    comp = sel & ~excluded
     return {"rays": int(len(ids)), "outside_band": int(far.sum()),
             "outcome_mismatch_outside_band": int(((st != ref["status"]) & far).sum()),
             "step_mismatch_fraction_outside_band": float(mism.sum() / max(1, far.sum())),
-            "step_mismatch_outside_1e-2_band_not_locked": int((mism & ~excluded).sum()),
+            "fallback_flips": int((flip & far).sum()),
+            "step_mismatch_outside_fp32c_exclusions": int((mism & ~excluded).sum()),
             "state_err": {"p50": float(np.percentile(e, 50)), "p99": float(np.percentile(e, 99)),
                           "max": float(e.max())} if e.size else None,
-            "state_err_outside_fp32c_exclusions_max": float(err[sel & ~excluded].max()) if (sel & ~excluded).any() else None,
+            "state_err_fp32c_rule": {"p50": float(np.percentile(err_m[comp], 50)),
+                                     "p99": float(np.percentile(err_m[comp], 99)),
+                                     "max": float(err_m[comp].max()),
+                                     "above_1e-3": int((err_m[comp] > 1e-3).sum())} if comp.any() else None,
             "fp32c_rule_excluded_fraction": float(excluded.mean()),
-            "fp32c_rule_excluded": {"within_1e-2_band": int((ref["band"] <= 1e-2).sum()),
+            "fp32c_rule_excluded": {"state_band_M": FP32C_STATE_BAND,
+                                    "within_state_band": int((ref["band"] <= FP32C_STATE_BAND).sum()),
                                     "euler_locked": int(locked.sum())}}
 
 
@@ -413,6 +433,7 @@ def measure(G, W, torch, np, cam, prec: str, steps: int, warmup: int, floor: boo
     # the pass's own results, copied before the floor measurement re-initialises the batch
     host = {"status": status, "steps": b.steps[: b.n].cpu().numpy(),
             "x": res.xf.view(8, b.stride)[:, : b.n].cpu().numpy().T if res.xf is not None else None,
+            "mark": b.mark.view(8, b.stride)[:, : b.n].cpu().numpy().T if b.mark is not None else None,
             "euler": euler, "band": band}
     tail = longest_alone(G, W, torch, np, b, params) if floor else None
     return {"params": params, "ms_per_step": ms_per_step, "integrate_ms": int_ms,
@@ -704,7 +725,9 @@ def c3_block(G, W, torch, np, with_oracle: bool, reps: int = 3) -> dict:
             # the sampled rays only, gathered on the device
             idx = torch.as_tensor(ids, dtype=torch.int64, device=b.x.device)
             g = {"status": b.status[idx].cpu().numpy(), "steps": b.steps[idx].cpu().numpy(),
-                 "x": res.xf.view(8, b.stride)[:, idx].cpu().numpy().T}
+                 "x": res.xf.view(8, b.stride)[:, idx].cpu().numpy().T,
+                 "euler": b.counters.view(3, b.stride)[0, idx].cpu().numpy(),
+                 "mark": b.mark.view(8, b.stride)[:, idx].cpu().numpy().T}
             blk["error_vs_oracle"] = error_vs_oracle(np, g, ref, gathered=True)
             dg = b.disk.view(3, b.stride)[:, idx].cpu().numpy().T
             agree = (g["status"] == ref["status"]) & (g["steps"] == ref["steps"])
