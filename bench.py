@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 256-camera sweep")
     ap.add_argument("--no-c3", action="store_true", help="skip the 4096x4096 recorder workload")
+    ap.add_argument("--no-steady", action="store_true", help="skip the far-field steady-state workload")
     ap.add_argument("--no-deformed", action="store_true", help="skip the deformed-metric timing")
     ap.add_argument("--no-ring", action="store_true", help="skip the photon-ring study")
     ap.add_argument("--no-pole", action="store_true", help="skip the pole-treatment ablation")
@@ -592,6 +593,9 @@ def main():
     }
     if args.precision == "fp32c":
         out["fp64_step_fraction"] = head["fp64_steps"] / total_steps
+    if not args.no_steady:
+        print("bench: far-field steady state", file=sys.stderr, flush=True)
+        out["steady"] = steady_block(G, W, torch, np)
     if not args.no_c3:
         print("bench: 4096x4096 recorder workload", file=sys.stderr, flush=True)
         out["c3"] = c3_block(G, W, torch, np, with_oracle=not args.no_cpu_baseline)
@@ -675,6 +679,34 @@ def deformed_block(G, W, torch, np, reps: int = 3) -> dict:
         del b, res
         torch.cuda.empty_cache()
     out["generic_over_fast_path_time"] = out["generic_0"]["integrate_ms"] / out["kerr_fast_path"]["integrate_ms"]
+    return out
+
+
+def steady_block(G, W, torch, np, reps: int = 5) -> dict:
+    """Throughput without a tail: a 2048 x 2048 grid aimed 200-300 M off the
+    hole (a = 0.9, i = 60 deg), every ray advanced exactly 100 far-field steps
+    (call_steps = 100), in both precisions: integrate time (best of `reps`,
+    HIP events), ns per photon-step and the VALU roofline."""
+    cam = W.Camera(0.9, 1000.0, W.deg(60.0), 2048, 2048, 200.0, 300.0, 200.0, 300.0)
+    out = {"workload": "far_field_a0.9_i60_2048x2048_100_steps", "photons": cam.n}
+    for prec in ("fp64", "fp32c"):
+        b = G.Batch([cam], W.Params(precision=prec, call_steps=100), mark=False)
+        ms = []
+        for _ in range(reps):
+            b.camera_init()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.integrate()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        steps = int(b.steps[: b.n].to(torch.int64).sum().item())
+        m = {"integrate_ms": min(ms), "total_steps": steps}
+        out[prec] = {"integrate_ms": min(ms), "photon_steps": steps, "ns_per_photon_step": min(ms) * 1e6 / steps,
+                     "roofline": roofline(prec, m, None)}
+        del b
+        torch.cuda.empty_cache()
+    out["fp32c_speedup_vs_fp64"] = out["fp64"]["integrate_ms"] / out["fp32c"]["integrate_ms"]
     return out
 
 
