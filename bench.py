@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 # Algorithmic flops per accepted photon-step of the integrate kernel (common
 # path: RK4 + step size + null-condition check), weights add/mul 1, fma 2,
 # div/sqrt/sin/cos 1; produced by csrc/flopcount.cpp and checked by the tests.
-F_STEP = {"fp64": 572, "fp32c": 572}
+F_STEP = {"fp64": 538, "fp32c": 538}
 # MI355X published vector peaks, TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 flops
 # x 2.4 GHz). FP32 reaches 157.3 only with packed (two-per-lane) FP32
 # instructions, which this library does not use; its float code issues at the
@@ -632,7 +632,7 @@ def roofline(prec: str, m: dict, traffic) -> dict:
     accepted photon-step times the launch's photon-steps over its HIP-event
     time."""
     achieved = F_STEP[prec] * m["total_steps"] / (m["integrate_ms"] * 1e-3) / 1e12
-    kernel = "k_integrate<GRAY_FP64, kPoleMonitor>" if prec == "fp64" else "k_integrate<GRAY_FP32C, kPoleMonitor>"
+    kernel = "k_integrate<kPoleMonitor>" if prec == "fp64" else "k_integrate_c32"
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic, "traffic_unit": "bytes per launch",
             "kernel": kernel, "flops_per_photon_step": F_STEP[prec]}

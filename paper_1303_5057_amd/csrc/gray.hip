@@ -569,56 +569,84 @@ struct Lane<GRAY_FP32C> {
     }
 };
 
-// x rounded to the nearest sum of two floats, the form in which the FP32C
-// state is stored.
-__device__ __forceinline__ State<double> pair_rounded(const State<double> &x)
-{
-    Lane<GRAY_FP32C> P;
-    P.split(x);
-    return P.value();
-}
-
-// FP64 step of the FP32C integrator (x in, the accepted state out; flags as
-// rk4_step). Rare (a null-monitor decision that float rounding cannot take,
-// a non-finite float proposal, or a caller-requested FP64 zone), so it is a
-// real call: the float loop then keeps the registers of the float step
-// only, and the call saves and restores what it clobbers.
-struct Step64 {
-    State<double> x;
-    int flags;
-};
-
-__device__ __noinline__ Step64 fp64_step(StepConst<double> K, State<double> x)
-{
-    double s, c;
-    sin_cos<false>(x.th, s, c);
-    Step64 out;
-    out.flags = rk4_step<kPoleMonitor, false>(K, x, s, c);
-    out.x = x;
-    return out;
-}
-
 __device__ __forceinline__ bool finite_state(const State<double> &x)
 {
     return isfinite(x.t) && isfinite(x.r) && isfinite(x.th) && isfinite(x.ph) && isfinite(x.kt) &&
            isfinite(x.kr) && isfinite(x.kth) && isfinite(x.kph);
 }
 
-// Persistent integrator. Each wave keeps 64 photons in registers; whenever at
-// least A.refill lanes are idle it hands them the next photons of the wave's
-// current 64-photon chunk, taking a new chunk from the global counter when the
-// old one is used up. A wave exits once the counter is past n and all its
-// lanes are idle; every photon ends within max_steps (or call_steps) steps,
-// so every wave exits. PM is the treatment of the polar axis (FP64 only;
-// the production monitor unless a caller asks for one of the paper's
-// earlier treatments), a template parameter so that the production kernel
-// carries no code for the others; MET selects the spacetime (Kerr, or the
-// deformed metric through the metric-generic right-hand side).
-template <int P, int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRAY_FP32C ? 3 : 1))) void k_integrate(IntArgs A)
+// Stop bookkeeping of the persistent loops, once per iteration (a
+// wave-uniform call): work-list output of the photons still running, written
+// into a private span of kSpan reserved slots per wave (when it fills up the
+// rest continues in a fresh span, so the only unused slots are the tail of
+// each wave's last span, marked -1 at exit), and the per-camera completion
+// counts (one atomic per wave when the photons that finished share a camera).
+struct StopBook {
+    unsigned span_next = 0, span_end = 0;
+    __device__ __forceinline__ void account(bool stop_now, bool keep, int64_t id, unsigned lane, bool list_out,
+                                            bool count_done)
+    {
+        if (list_out) {
+            const uint64_t m = ballot(keep);
+            const unsigned cnt = (unsigned)__popcll(m);
+            if (cnt) {
+                const unsigned room = span_end - span_next;
+                unsigned fresh = 0;
+                if (cnt > room) {
+                    if (lane == 0) fresh = atomicAdd(GRAY_ARG(work_out_count), kSpan);
+                    fresh = __builtin_amdgcn_readfirstlane(fresh);
+                }
+                const unsigned r = lane_rank(m);
+                if (keep) glob(GRAY_ARG(work_out))[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
+                if (cnt > room) {
+                    span_next = fresh + (cnt - room);
+                    span_end = fresh + kSpan;
+                } else {
+                    span_next += cnt;
+                }
+            }
+        }
+        if (count_done) {
+            const bool fin = stop_now && !keep;
+            const uint64_t mf = ballot(fin);
+            if (mf) {
+                const int32_t c = fin ? glob(GRAY_ARG(cam))[id] : -1;
+                const unsigned lead = (unsigned)(__ffsll((long long)mf) - 1);
+                const int32_t cl = __shfl(c, (int)lead, kWave);
+                if (ballot(fin && c != cl) == 0ull) {
+                    if (lane == lead) atomicAdd(GRAY_ARG(cam_done) + cl, (unsigned)__popcll(mf));
+                } else if (fin) {
+                    atomicAdd(GRAY_ARG(cam_done) + c, 1u);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void finish(unsigned lane, bool list_out, unsigned long long iters)
+    {
+        if (list_out) {
+            global_ptr<int32_t> wo = glob(GRAY_ARG(work_out));
+            for (unsigned j = span_next + lane; j < span_end; j += kWave) wo[j] = -1;
+        }
+        if (unsigned long long *wi = GRAY_ARG(wave_iters))
+            if (lane == 0 && iters) atomicAdd(wi, iters);
+    }
+};
+
+// Persistent integrator (FP64). Each wave keeps 64 photons in registers;
+// whenever at least A.refill lanes are idle it hands them the next photons of
+// the wave's current chunk of the queue, taking a new chunk from the global
+// counter when the old one is used up. A wave exits once the counter is past
+// the queue length and all its lanes are idle; every photon ends within
+// max_steps (or call_steps) steps, so every wave exits. PM is the treatment of
+// the polar axis (the production monitor unless a caller asks for one of the
+// paper's earlier treatments), a template parameter so that the production
+// kernel carries no code for the others; MET selects the spacetime (Kerr, or
+// the deformed metric through the metric-generic right-hand side).
+template <int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR>
+__global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
-    static_assert(MET == GRAY_METRIC_KERR || (P == GRAY_FP64 && PM == kPoleMonitor),
-                  "the deformed metric is integrated in FP64 with the production pole treatment");
+    static_assert(MET == GRAY_METRIC_KERR || PM == kPoleMonitor,
+                  "the deformed metric is integrated with the production pole treatment");
     using Space = typename std::conditional<MET == GRAY_METRIC_DEFORMED, DeformedSpin, Spin<double>>::type;
     const unsigned lane = threadIdx.x & (kWave - 1);
     const bool record_disk = (A.flags & GRAY_RECORD_DISK) != 0;
@@ -628,16 +656,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRA
 
     bool active = false;
     int64_t id = 0;
-    Lane<P> L;
+    Lane<GRAY_FP64> L;
     StepConst<double, Space> K;
-    StepConst<float> Kf;
-    FloatHorizon Hf{};
     double rcap = 0.0, resc = 0.0;
-    // FP32C: float thresholds of the photon (FP64 zone, capture and mark
-    // radii, the mark band) and of the call (pole, turning point, escape)
-    float r64 = 0.0f, rcap_f = 0.0f, rmark_f = 0.0f, rband_f = 0.0f;
-    const float pole_f = (float)A.fp64_pole, turn_f = (float)A.fp64_turn;
-    const float resc_f = (float)(A.r_escape * (1.0 - 1e-6));
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
 
@@ -661,8 +682,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRA
     int64_t rounds = nq / (waves * kQueueChunk * 4);
     rounds = rounds < 1 ? 1 : (rounds > kMaxGrab ? kMaxGrab : rounds);
     const unsigned grab = (unsigned)rounds * kQueueChunk;
-    // Work-list output: a private span of kSpan reserved slots per wave.
-    unsigned span_next = 0, span_end = 0;
+    StopBook book;
     unsigned long long iters = 0;
 
     for (;;) {
@@ -713,18 +733,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRA
                         K.step_frac = A.step_frac;
                         K.xi_eps = A.xi_eps;
                         K.euler_inv = A.euler_inv;
-                        if constexpr (P == GRAY_FP32C) {
-                            Kf.B = make_spin((float)cm.a);
-                            Kf.rbh = (float)cm.rbh;
-                            Kf.step_frac = (float)A.step_frac;
-                            Kf.xi_eps = (float)A.xi_eps;
-                            Kf.euler_inv = (float)A.euler_inv;
-                            Hf = make_float_horizon(cm.a);
-                            r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
-                            rcap_f = (float)(cm.rcap * (1.0 + 1e-6));
-                            rmark_f = (float)cm.rmark;
-                            rband_f = (float)(cm.rmark * (1.0 + 2.0 * A.step_frac));
-                        }
                         rcap = cm.rcap;
                         resc = A.r_escape;
                         nsteps = glob(PA.steps)[id];
@@ -746,13 +754,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRA
                 chunk_next += taken;
             }
             if (exhausted && chunk_next >= chunk_end && ballot(active) == 0ull) {
-                // mark the unused rest of this wave's output span
-                if (list_out) {
-                    global_ptr<int32_t> wo = glob(GRAY_ARG(work_out));
-                    for (unsigned j = span_next + lane; j < span_end; j += kWave) wo[j] = -1;
-                }
-                if (unsigned long long *wi = GRAY_ARG(wave_iters))
-                    if (lane == 0 && iters) atomicAdd(wi, iters);
+                book.finish(lane, list_out, iters);
                 break;
             }
         }
@@ -761,101 +763,45 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRA
         iters += ballot(active) != 0ull;
         if (active) {
             // Equatorial-crossing recorder and 2 r_bh mark of one accepted
-            // step from xp to x (each a rare event, tested wave-wide first).
-            // Equatorial-crossing recorder of one accepted step from
-            // (pth, pr, pph) to x, and the 2 r_bh mark, each a rare event
-            // tested wave-wide first.
-            auto record_disk_event = [&](double pth, double pr, double pph, const State<double> &x) {
-                const bool cross = record_disk && !hit && (pth - kHalfPi) * (x.th - kHalfPi) < 0.0;
+            // step from xp to x, each a rare event tested wave-wide first.
+            auto record = [&](const State<double> &xp, const State<double> &x) {
+                const bool cross = record_disk && !hit && (xp.th - kHalfPi) * (x.th - kHalfPi) < 0.0;
                 if (record_disk && __builtin_expect(any_lane(cross), 0) && cross) {
-                    const double f = (kHalfPi - pth) / (x.th - pth);
-                    const double rc = pr + f * (x.r - pr);
+                    const double f = (kHalfPi - xp.th) / (x.th - xp.th);
+                    const double rc = xp.r + f * (x.r - xp.r);
                     // recorder window of the photon's camera, read when needed
                     const DevCam &cw = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
                     if (rc >= cw.disk_rmin && rc <= cw.disk_rmax) {
                         double E, Lz, Q, sx, cx;
-                        sin_cos<P == GRAY_FP64>(x.th, sx, cx);
+                        sin_cos<true>(x.th, sx, cx);
                         conserved_sc(K.B.a, x, sx, cx, E, Lz, Q);
                         Column<double> D(GRAY_ARG(disk), A.stride, id);
                         D.put(rc);
                         D.next();
-                        D.put(pph + f * (x.ph - pph));
+                        D.put(xp.ph + f * (x.ph - xp.ph));
                         D.next();
                         D.put(disk_redshift(K.B.a, rc, E, Lz));
                         hit = true;
                     }
                 }
-            };
-            auto write_mark = [&](const State<double> &xp) {
-                const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
-                Column<double> M(GRAY_ARG(mark), A.stride, id);
-                for (int k = 0; k < 8; ++k) {
-                    M.put(v[k]);
-                    if (k < 7) M.next();
-                }
-            };
-            auto record = [&](const State<double> &xp, const State<double> &x) {
-                record_disk_event(xp.th, xp.r, xp.ph, x);
                 const double rmark = K.rbh + K.rbh;
                 const bool inward = xp.r >= rmark && x.r < rmark;
-                if (record_mark && __builtin_expect(any_lane(inward), 0) && inward) write_mark(xp);
-            };
-            int fl;
-            int32_t st = GRAY_RUNNING;
-            if constexpr (P == GRAY_FP64) {
-                fl = rk4_step<PM>(K, L.x, L.s, L.c, record);
-                const State<double> &x = L.x;
-                st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
-                st = (x.r > resc && x.kr > 0.0) ? GRAY_ESCAPED : st;
-                st = x.r < rcap ? GRAY_CAPTURED : st;
-                st = (fl < 0 || !finite_state(x)) ? GRAY_NONFINITE : st;
-            } else {
-                auto &F = L;
-                // The step is taken in float (rk4_step_f32); in FP64 when the
-                // float step cannot decide the null monitor (or its proposal
-                // is not finite), and, if the caller asks for it, inside the
-                // optional zones near the horizon, a pole or a radial turning
-                // point.
-                const bool need64 = F.hi.r < r64 || F.s < pole_f || fabsf(F.hi.kr) < turn_f * fabsf(F.hi.kt);
-                // A photon at r in [2 r_bh, 2 r_bh (1 + 2 Delta)) may fall below
-                // 2 r_bh in this step (a step moves r by at most about Delta r):
-                // its state is kept as the mark before a float step.
-                const bool band = record_mark && !need64 && F.hi.r >= rmark_f && F.hi.r < rband_f;
-                if (__builtin_expect(any_lane(band), 0) && band) write_mark(F.value());
-                const float pth = F.hi.th, pr = F.hi.r, pph = F.hi.ph;
-                fl = -2;
-                if (any_lane(!need64) && !need64) fl = rk4_step_f32(Kf, Hf, F.hi, F.lo, F.s, F.c);
-                const bool flt = fl >= 0;
-                if (__builtin_expect(any_lane(fl == -2), 0) && fl == -2) {
-                    const State<double> x0 = F.value();
-                    Step64 r64s = fp64_step(K, x0);
-                    fl = r64s.flags;
-                    if (fl >= 0) {
-                        record(x0, r64s.x);
-                        F.set(r64s.x);
-                        ++n64;
+                if (record_mark && __builtin_expect(any_lane(inward), 0) && inward) {
+                    const double v[8] = {xp.t, xp.r, xp.th, xp.ph, xp.kt, xp.kr, xp.kth, xp.kph};
+                    Column<double> M(GRAY_ARG(mark), A.stride, id);
+                    for (int k = 0; k < 8; ++k) {
+                        M.put(v[k]);
+                        if (k < 7) M.next();
                     }
                 }
-                if (record_disk && flt) {
-                    const bool cross = !hit && (pth - (float)kHalfPi) * (F.hi.th - (float)kHalfPi) <= 0.0f;
-                    if (__builtin_expect(any_lane(cross), 0) && cross)
-                        record_disk_event(pth, pr, pph, F.value());
-                }
-                // Termination tests on the float high words, exact (hi + lo in
-                // FP64) only for photons within a relative 1e-6 of a threshold.
-                st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
-                const bool near = F.hi.r < rcap_f || (F.hi.r > resc_f && F.hi.kr >= 0.0f);
-                if (__builtin_expect(any_lane(near), 0) && near) {
-                    const double xr = (double)F.hi.r + (double)F.lo.r;
-                    const double xkr = (double)F.hi.kr + (double)F.lo.kr;
-                    st = (xr > resc && xkr > 0.0) ? GRAY_ESCAPED : st;
-                    st = xr < rcap ? GRAY_CAPTURED : st;
-                }
-                const bool finite = isfinite(F.hi.t) && isfinite(F.hi.r) && isfinite(F.hi.th) &&
-                                    isfinite(F.hi.ph) && isfinite(F.hi.kt) && isfinite(F.hi.kr) &&
-                                    isfinite(F.hi.kth) && isfinite(F.hi.kph);
-                st = (fl < 0 || !finite) ? GRAY_NONFINITE : st;
-            }
+            };
+            const int fl = rk4_step<PM>(K, L.x, L.s, L.c, record);
+            const State<double> &x = L.x;
+            int32_t st = GRAY_RUNNING;
+            st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
+            st = (x.r > resc && x.kr > 0.0) ? GRAY_ESCAPED : st;
+            st = x.r < rcap ? GRAY_CAPTURED : st;
+            st = (fl < 0 || !finite_state(x)) ? GRAY_NONFINITE : st;
             // counters after the step, taken with selects (no per-lane branch)
             const bool ok = fl >= 0;
             nsteps += ok;
@@ -882,48 +828,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == GRA
                 active = false;
             }
         }
-
-        // Wave-uniform bookkeeping of the photons that stopped this iteration.
-        if (list_out) {
-            // Photons still running go on the next work list, written into
-            // the wave's reserved span; when it fills up the rest continues
-            // in a fresh span of kSpan slots, so the only unused slots are
-            // the tail of each wave's last span (marked -1 at exit).
-            const uint64_t m = ballot(keep);
-            const unsigned cnt = (unsigned)__popcll(m);
-            if (cnt) {
-                const unsigned room = span_end - span_next;
-                unsigned fresh = 0;
-                if (cnt > room) {
-                    if (lane == 0) fresh = atomicAdd(GRAY_ARG(work_out_count), kSpan);
-                    fresh = __builtin_amdgcn_readfirstlane(fresh);
-                }
-                const unsigned r = lane_rank(m);
-                if (keep) glob(GRAY_ARG(work_out))[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
-                if (cnt > room) {
-                    span_next = fresh + (cnt - room);
-                    span_end = fresh + kSpan;
-                } else {
-                    span_next += cnt;
-                }
-            }
-        }
-        if (count_done) {
-            // Completion count per camera: one atomic per wave when the
-            // photons that finished share a camera.
-            const bool fin = stop_now && !keep;
-            const uint64_t mf = ballot(fin);
-            if (mf) {
-                const int32_t c = fin ? glob(GRAY_ARG(cam))[id] : -1;
-                const unsigned lead = (unsigned)(__ffsll((long long)mf) - 1);
-                const int32_t cl = __shfl(c, (int)lead, kWave);
-                if (ballot(fin && c != cl) == 0ull) {
-                    if (lane == lead) atomicAdd(GRAY_ARG(cam_done) + cl, (unsigned)__popcll(mf));
-                } else if (fin) {
-                    atomicAdd(GRAY_ARG(cam_done) + c, 1u);
-                }
-            }
-        }
+        book.account(stop_now, keep, id, lane, list_out, count_done);
     }
 }
 
@@ -975,59 +880,6 @@ __device__ __forceinline__ void lds_store(unsigned *p, unsigned v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-
-// Stop bookkeeping shared by both loops: work-list output of the photons
-// still running and the per-camera completion counts (wave-uniform call).
-struct StopBook {
-    unsigned span_next = 0, span_end = 0;
-    __device__ __forceinline__ void account(bool stop_now, bool keep, int64_t id, unsigned lane, bool list_out,
-                                            bool count_done)
-    {
-        if (list_out) {
-            const uint64_t m = ballot(keep);
-            const unsigned cnt = (unsigned)__popcll(m);
-            if (cnt) {
-                const unsigned room = span_end - span_next;
-                unsigned fresh = 0;
-                if (cnt > room) {
-                    if (lane == 0) fresh = atomicAdd(GRAY_ARG(work_out_count), kSpan);
-                    fresh = __builtin_amdgcn_readfirstlane(fresh);
-                }
-                const unsigned r = lane_rank(m);
-                if (keep) glob(GRAY_ARG(work_out))[r < room ? span_next + r : fresh + (r - room)] = (int32_t)id;
-                if (cnt > room) {
-                    span_next = fresh + (cnt - room);
-                    span_end = fresh + kSpan;
-                } else {
-                    span_next += cnt;
-                }
-            }
-        }
-        if (count_done) {
-            const bool fin = stop_now && !keep;
-            const uint64_t mf = ballot(fin);
-            if (mf) {
-                const int32_t c = fin ? glob(GRAY_ARG(cam))[id] : -1;
-                const unsigned lead = (unsigned)(__ffsll((long long)mf) - 1);
-                const int32_t cl = __shfl(c, (int)lead, kWave);
-                if (ballot(fin && c != cl) == 0ull) {
-                    if (lane == lead) atomicAdd(GRAY_ARG(cam_done) + cl, (unsigned)__popcll(mf));
-                } else if (fin) {
-                    atomicAdd(GRAY_ARG(cam_done) + c, 1u);
-                }
-            }
-        }
-    }
-    __device__ __forceinline__ void finish(unsigned lane, bool list_out, unsigned long long iters)
-    {
-        if (list_out) {
-            global_ptr<int32_t> wo = glob(GRAY_ARG(work_out));
-            for (unsigned j = span_next + lane; j < span_end; j += kWave) wo[j] = -1;
-        }
-        if (unsigned long long *wi = GRAY_ARG(wave_iters))
-            if (lane == 0 && iters) atomicAdd(wi, iters);
-    }
-};
 
 // Store one photon's counters and state at a stop (either loop).
 __device__ __forceinline__ void c32_store(const Lane<GRAY_FP32C> &L, int64_t id, int32_t st, int32_t nsteps,
@@ -1288,9 +1140,10 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
 }
 
 // FP64 phase of a block's FP64 wave: photons handed over by the block's
-// waves, FP64 steps on the compensated pair (the state is rounded to hi + lo
-// after every step, so a resumed call continues bit for bit), until they
-// stop. Returns true when the wave is done (the float waves of its block
+// waves, FP64 steps on the compensated pair until they stop. Each step
+// rounds the state to 48-bit significands, which the float pair holds
+// exactly, and takes its sin/cos there, so a resumed call (which rebuilds
+// the state from the pair) continues bit for bit. Returns true when the wave is done (the float waves of its block
 // have exited and every handed-over photon has stopped), false when it has
 // nothing to do but the global queue may still hold float work.
 __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, unsigned nfloat_waves, WaveCtx &W)
@@ -1304,16 +1157,27 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
     bool active = false;
     int64_t id = 0;
     State<double> x{};   // always a sum hi + lo of two floats
+    double s64 = 0.0, c64 = 1.0;   // sin and cos of x.th
     StepConst<double, Spin<double>> K;
     double rcap = 0.0;
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
     StopBook &book = W.book;
     unsigned long long &iters = W.iters;
+    // The queue is closed once the block's float waves have exited (every
+    // slot they reserved is then published) and every slot has been taken:
+    // nothing more can arrive, and the wave stops polling.
+    bool closed = false;
+    unsigned tick = 0;
 
     for (;;) {
         const uint64_t idle = ballot(!active);
-        if (idle) {
+        // Poll while the queue may still receive photons: whenever every lane
+        // or a quarter of the lanes are idle, otherwise every fourth
+        // iteration (a wave with few photons left spends little of its step
+        // on the queue's loads).
+        ++tick;
+        if (idle && !closed && (idle == ~0ull || __popcll(idle) >= kWave / 4 || (tick & 3u) == 0u)) {
             const unsigned done = __hip_atomic_load(&Q.float_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
             const unsigned h = __builtin_amdgcn_readfirstlane(lds_load(&Q.head));
             const unsigned t = __builtin_amdgcn_readfirstlane(lds_load(&Q.tail));
@@ -1337,6 +1201,7 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
                     hit = Q.hit[s] != 0;
                     double *xp = &x.t;
                     for (int k = 0; k < 8; ++k) xp[k] = (double)Q.hi[k][s] + (double)Q.lo[k][s];
+                    sin_cos<true>(x.th, s64, c64);
                     const DevCam cm = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
                     K.B = make_spin(cm.a);
                     K.rbh = cm.rbh;
@@ -1350,12 +1215,17 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 if (took) lds_store(&Q.ready[(h + rank) % kHandCap], 0u);
                 if (lane == 0) lds_store(&Q.head, h + c);
-            } else if (idle == ~0ull) {
-                if (done == nfloat_waves && h == t) return true;
-                if (!W.exhausted && A.helper) return false;
-                __builtin_amdgcn_s_sleep(2);
-                continue;
+            } else {
+                closed = done == nfloat_waves && h == t;
+                if (idle == ~0ull) {
+                    if (closed) return true;
+                    if (!W.exhausted && A.helper) return false;
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
             }
+        } else if (closed && idle == ~0ull) {
+            return true;
         }
 
         bool stop_now = false, keep = false;
@@ -1394,13 +1264,8 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
                     }
                 }
             };
-            double s64, c64;
-            sin_cos<true>(x.th, s64, c64);
-            const int fl = rk4_step<kPoleMonitor, true>(K, x, s64, c64, record);
-            if (fl >= 0) {
-                x = pair_rounded(x);
-                ++n64;
-            }
+            // (the step rounds the state to the float pair it is stored as)
+            const int fl = rk4_step<kPoleMonitor, true, true>(K, x, s64, c64, record);
             const State<double> &xr = x;
             int32_t st = GRAY_RUNNING;
             st = nsteps + (fl >= 0) >= A.max_steps ? GRAY_UNFINISHED : st;
@@ -1412,6 +1277,7 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
             ncall += ok;
             ne += ok ? (fl & 1) : 0;
             nr += ok ? ((fl >> 1) & 1) : 0;
+            n64 += ok;
             const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
             if (__builtin_expect(any_lane(stop), 0) && stop) {
                 Lane<GRAY_FP32C> P;
@@ -1749,9 +1615,9 @@ static int device_info(DeviceInfo &out)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
         const void *kernels[kVariants] = {
-            (const void *)k_integrate<GRAY_FP64, kPoleMonitor>, (const void *)k_integrate_c32,
-            (const void *)k_integrate<GRAY_FP64, kPoleEulerCrossing>, (const void *)k_integrate<GRAY_FP64, kPoleNone>,
-            (const void *)k_integrate<GRAY_FP64, kPoleMonitor, GRAY_METRIC_DEFORMED>};
+            (const void *)k_integrate<kPoleMonitor>, (const void *)k_integrate_c32,
+            (const void *)k_integrate<kPoleEulerCrossing>, (const void *)k_integrate<kPoleNone>,
+            (const void *)k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED>};
         for (int v = 0; v < kVariants; ++v) {
             int nb = 0;
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[v], kBlock, 0);
@@ -2000,12 +1866,12 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave)) : blocks_for(s->n);
     const unsigned grid = (unsigned)(need < resident ? need : resident);
     switch (variant) {
-    case 0: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 0: hipLaunchKernelGGL((k_integrate<kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
     case 1: hipLaunchKernelGGL(k_integrate_c32, dim3(grid), dim3(kBlock), 0, st, A); break;
-    case 2: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleEulerCrossing>), dim3(grid), dim3(kBlock), 0, st, A); break;
-    case 3: hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 2: hipLaunchKernelGGL((k_integrate<kPoleEulerCrossing>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 3: hipLaunchKernelGGL((k_integrate<kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
     default:
-        hipLaunchKernelGGL((k_integrate<GRAY_FP64, kPoleMonitor, GRAY_METRIC_DEFORMED>), dim3(grid), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED>), dim3(grid), dim3(kBlock), 0, st,
                            A);
         break;
     }

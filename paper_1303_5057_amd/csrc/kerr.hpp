@@ -300,16 +300,20 @@ GRAY_HD Spin<T> make_spin(T a)
 // Geodesic acceleration given sin and cos of theta (see the file comment),
 // written out operation by operation: one reciprocal of Sigma Delta sin gives
 // 1/Sigma, 1/Delta and cot; every contraction is shaped into fused
-// multiply-adds. With rho^2 = r^2 + a^2 the identity rho^2 - a^2 sin^2 = Sigma
+// multiply-adds, and products that several terms share (w P, k^r k^th) are
+// formed once. With rho^2 = r^2 + a^2 the identity rho^2 - a^2 sin^2 = Sigma
 // gives the short forms used below:
 //   X = (a k^t - rho^2 k^phi) / Sigma  = a P / Sigma - k^phi,
-//   P cot = cot k^t - a sin cos k^phi, with P = k^t - a sin^2 k^phi,
-//   a^2 k^t^2 - 2 a rho^2 k^t k^phi + a^2 sin^2 rho^2 k^phi^2
-//                                       = Sigma^2 X^2 - rho^2 Sigma k^phi^2.
-// At2 and Aph2 are half of the lowered components A_t and A_phi / sin^2.
+//   F - 2 q rho^2 = Delta (F = g_phph / sin^2), so that
+//   F k^phi - 2 a q W P = Delta k^phi - 2 q rho^2 X   (W = rho^2 / Sigma) and
+//   the k^phi^2 coefficient of A_th is -Delta,
+//   (Delta / Sigma) (1/2) d_r g_rr = q - (r - 1) / Delta.
+// At2 and Aph2 are half of the lowered components A_t and A_phi / sin^2;
+// dk^r = -(Delta / Sigma) A_r is formed without A_r.
 // Given Delta = r^2 - 2 r + a^2 (the float step passes it in factored form,
 // (r - r_+)(r - r_-) with r - r_+ from the compensated state, which keeps its
-// digits next to the horizon).
+// digits next to the horizon; Delta enters directly where the earlier forms
+// took it as a difference of two larger terms).
 template <class T>
 GRAY_HD void accel_del(const Spin<T> &B, T r, T del, T s, T c, T kt, T kr, T kth, T kph, T &dkt, T &dkr,
                        T &dkth, T &dkph)
@@ -329,35 +333,33 @@ GRAY_HD void accel_del(const Spin<T> &B, T r, T del, T s, T c, T kt, T kr, T kth
     const T q = r * isig;                                    // r / Sigma
     const T q2 = q + q;
     const T w = fma(-q2, q, isig);                           // (Sigma - 2 r^2) / Sigma^2
-    const T W = rho2 * isig;
-    const T F = fma(a2 * s2, q2, rho2);                      // g_phiphi / sin^2
-    const T hdrgrr = idel * fma(-(sig * idel), r - T(1), r); // (1/2) d_r g_rr
     const T P = fma(-(a * s2), kph, kt);
-    const T kr2 = kr * kr, kth2 = kth * kth, kph2 = kph * kph;
-    const T aq2 = a * q2;                                    // 2 a r / Sigma
-    const T idel2 = idel + idel;
+    const T wP = w * P;
     const T X = fma(a * isig, P, -kph);
+    const T kr2 = kr * kr, kth2 = kth * kth, kph2 = kph * kph;
+    const T krth = kr * kth;
+    const T aq2 = a * q2;                                    // 2 a r / Sigma
     const T r_2 = r + r;
 
     // A_t / 2
-    const T At2 = fma(w * kr, P, ((aq2 * sc) * kth) * X);
+    const T At2 = fma(wP, kr, ((aq2 * sc) * kth) * X);
     // A_phi / (2 sin^2)
-    const T t1 = fma(-(a * w), P, r * kph);
-    const T Aph2 = fma(kth * cot, fma(-(aq2 * W), P, F * kph), kr * t1);
-    // A_r
-    T Ar = hdrgrr * kr2;
-    Ar = fma(-((a2 * sc) * idel2 * kr), kth, Ar);
-    Ar = fma(-r, fma(s2, kph2, kth2), Ar);
-    Ar = fma(-(w * P), P, Ar);
+    const T t1 = fma(-a, wP, r * kph);
+    const T Aph2 = fma(kth * cot, fma(del, kph, -((q2 * rho2) * X)), kr * t1);
+    // -A_r Delta / Sigma
+    const T Tr = fma(r, fma(s2, kph2, kth2), wP * P);
+    T mAr = fma(-fma(T(1) - r, idel, q), kr2, (del * isig) * Tr);
+    mAr = fma((a2 * sc) * (isig + isig), krth, mAr);
     // A_theta = sin cos g + 2 r k^r k^theta
-    const T G = fma(-q2, rho2, F);
     T g = a2 * fma(idel, kr2, -kth2);
-    g = fma(-G, kph2, g);
+    g = fma(-del, kph2, g);
     g = fma(-(r_2 * X), X, g);
-    const T Ath = fma(sc, g, (r_2 * kr) * kth);
+    const T Ath = fma(sc, g, r_2 * krth);
 
+    const T F = fma(a2 * s2, q2, rho2);                      // g_phiphi / sin^2
+    const T idel2 = idel + idel;
     dkt = fma(aq2 * s2, Aph2, F * At2) * idel2;
-    dkr = -Ar * (del * isig);
+    dkr = mAr;
     dkth = -Ath * isig;
     dkph = fma(fma(T(2), q, T(-1)), Aph2, aq2 * At2) * idel2;
 }
@@ -421,26 +423,23 @@ GRAY_HD Metric<T> metric(T a, T a2, T r, T s, T c)
 }
 
 // Null-condition test of eq. (4) at (r, theta) given sin/cos of theta, free
-// of divisions: |xi + 1| > eps  <=>  |N + g_tt kt^2| > eps |g_tt kt^2| with N
-// the numerator of xi, and the metric components times Sigma Delta (a factor
-// that changes neither side) are polynomials,
-//   g_tt Sigma Delta = (2 r - Sigma) Delta,   g_tph Sigma Delta = -2 a r sin^2 Delta,
-//   g_rr Sigma Delta = Sigma^2,   g_thth Sigma Delta = Sigma^2 Delta,
-//   g_phph Sigma Delta = (rho^2 Sigma + 2 a^2 r sin^2) sin^2 Delta.
+// of divisions: |xi + 1| > eps  <=>  |N + D| > eps |D| with N the numerator
+// of xi and D = g_tt kt^2, both multiplied by Sigma Delta (a factor that
+// changes neither side). N + D is then Sigma Delta g(k, k); writing the t-phi
+// block as -(Delta / Sigma) P^2 + (sin^2 / Sigma) Y^2 with P = kt - a sin^2 kph
+// and Y = a kt - rho^2 kph = a P - Sigma kph,
+//   Sigma Delta g(k, k) = Sigma^2 kr^2 + Delta (Sigma^2 kth^2 + sin^2 Y^2) - Delta^2 P^2,
+//   Sigma Delta g_tt    = (2 r - Sigma) Delta.
 template <class T>
 GRAY_HD bool xi_violated_del(T a, T a2, T r, T del, T s, T c, T kt, T kr, T kth, T kph, T eps)
 {
-    const T s2 = s * s;
-    const T r2 = r * r;
-    const T sig = fma(a2, c * c, r2);
-    const T sig2 = sig * sig;
-    const T ar2 = (a + a) * r;                           // 2 a r
-    const T phph = fma(ar2 * a, s2, (r2 + a2) * sig);    // rho^2 Sigma + 2 a^2 r sin^2
-    T inner = fma(sig2, kth * kth, phph * (s2 * kph) * kph);
-    inner = fma(-(ar2 + ar2) * (s2 * kt), kph, inner);
-    const T num = fma(del, inner, sig2 * (kr * kr));
+    const T sig = fma(a2, c * c, r * r);
+    const T P = fma(-(a * (s * s)), kph, kt);
+    const T sY = s * fma(a, P, -(sig * kph));
+    const T skth = sig * kth, skr = sig * kr, dP = del * P;
+    const T gkk = fma(del, fma(skth, skth, sY * sY), fma(skr, skr, -(dP * dP)));
     const T den = ((r + r - sig) * del) * (kt * kt);
-    return fabs(num + den) > eps * fabs(den);
+    return fabs(gkk) > eps * fabs(den);
 }
 
 template <class T>
@@ -592,7 +591,10 @@ struct StepConst {
 // step. (s, c) = sin/cos(x.th) on entry and
 // on exit (always recomputed from the final theta, so a step is a function of
 // the stored state alone). Returns bit 0 = Euler fallback, bit 1 = remap, or
-// -1 when h is not a positive finite number (state kept).
+// -1 when h is not a positive finite number (state kept). With R48 (FP64
+// only) the accepted state is rounded to 48-bit significands (round48)
+// before its sin/cos and the null test are taken, so that it is exactly the
+// float pair the compensated-float path stores.
 // sin/cos helpers of the step template: the FP64 versions take the
 // coefficient placement SC, other number types use their own overloads.
 template <bool SC, class T>
@@ -609,13 +611,30 @@ GRAY_HD void step_sin_cos(T x, T &s, T &c)
     else sin_cos(x, s, c);
 }
 
+// x with the low five bits of its 53-bit significand cleared (rounded toward
+// zero to 48 bits). Such a value is exactly hi + lo with hi = x rounded to
+// float and lo = x - hi, both floats (for |x| above about 1e-30, where lo is
+// not below the float range): the pair the compensated-float state stores.
+// One integer AND on the low word.
+GRAY_HD double round48(double x)
+{
+    return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) & ~0x1Full);
+}
+
+template <class T>
+GRAY_HD void round48_state(State<T> &x)
+{
+    x.t = round48(x.t); x.r = round48(x.r); x.th = round48(x.th); x.ph = round48(x.ph);
+    x.kt = round48(x.kt); x.kr = round48(x.kr); x.kth = round48(x.kth); x.kph = round48(x.kph);
+}
+
 // Step observer that does nothing (see rk4_step).
 struct NoObserver {
     template <class S>
     GRAY_HD void operator()(const S &, const S &) const {}
 };
 
-template <int PM = kPoleMonitor, bool SC = true, class T, class SP, class Obs = NoObserver>
+template <int PM = kPoleMonitor, bool SC = true, bool R48 = false, class T, class SP, class Obs = NoObserver>
 GRAY_HD int rk4_step(const StepConst<T, SP> &K, State<T> &x, T &s, T &c, Obs &&observe = Obs())
 {
     // eq. (2): h1 = Delta r / D1 with D1 = |k^r| + r (|k^th| + |k^ph|), and
@@ -626,7 +645,7 @@ GRAY_HD int rk4_step(const StepConst<T, SP> &K, State<T> &x, T &s, T &c, Obs &&o
     const T n2 = x.r - K.rbh;
     const T d2 = akr + akr;
     const bool second = (x.kr != T(0)) && (n2 * D1 < d2 * n1);
-    const T h = second ? quot(n2, d2) : quot(n1, D1);
+    const T h = quot(second ? n2 : n1, second ? d2 : D1);
     const bool hbad = !(h > T(0) && h < T(INFINITY));
     if (__builtin_expect(any_lane(hbad), 0))
         if (hbad) return -1;
@@ -637,17 +656,20 @@ GRAY_HD int rk4_step(const StepConst<T, SP> &K, State<T> &x, T &s, T &c, Obs &&o
     // for the Euler fallback.
     State<T> k1, k, y, acc;
     T sy, cy;
+    // (a stage's sin/cos from the angle addition formula with the offset
+    // h k^th itself; the stage's theta is needed only where the offset is
+    // too large for the series)
     deriv(K.B, x, s, c, k1);
     y = axpy(x, hh, k1);
-    step_shift_sincos<SC>(s, c, y.th - x.th, y.th, sy, cy);
+    step_shift_sincos<SC>(s, c, hh * k1.th, y.th, sy, cy);
     deriv(K.B, y, sy, cy, k);
     acc = axpy(k1, T(2), k);
     y = axpy(x, hh, k);
-    step_shift_sincos<SC>(s, c, y.th - x.th, y.th, sy, cy);
+    step_shift_sincos<SC>(s, c, hh * k.th, y.th, sy, cy);
     deriv(K.B, y, sy, cy, k);
     acc = axpy(acc, T(2), k);
     y = axpy(x, h, k);
-    step_shift_sincos<SC>(s, c, y.th - x.th, y.th, sy, cy);
+    step_shift_sincos<SC>(s, c, h * k.th, y.th, sy, cy);
     deriv(K.B, y, sy, cy, k);
 
     const T h6 = h * T(1.0 / 6.0);
@@ -656,6 +678,7 @@ GRAY_HD int rk4_step(const StepConst<T, SP> &K, State<T> &x, T &s, T &c, Obs &&o
     GRAY_RK4(t); GRAY_RK4(r); GRAY_RK4(th); GRAY_RK4(ph);
     GRAY_RK4(kt); GRAY_RK4(kr); GRAY_RK4(kth); GRAY_RK4(kph);
 #undef GRAY_RK4
+    if constexpr (R48) round48_state(xn);
 
     int flags = 0;
     step_sin_cos<SC>(xn.th, sy, cy);
@@ -678,6 +701,7 @@ GRAY_HD int rk4_step(const StepConst<T, SP> &K, State<T> &x, T &s, T &c, Obs &&o
         xn.ph = up ? xn.ph + T(kPi) : (down ? xn.ph - T(kPi) : xn.ph);
         xn.kth = (up || down) ? -xn.kth : xn.kth;
         flags |= (up || down) ? 2 : 0;
+        if constexpr (R48) round48_state(xn);
         T sf, cf;
         step_sin_cos<SC>(xn.th, sf, cf);
         sy = flags ? sf : sy;
@@ -697,64 +721,6 @@ GRAY_HD void two_sum(float a, float b, float &hi, float &lo)
     const float z = t - a;
     lo = (a - (t - z)) + (b - z);
     hi = t;
-}
-
-// One FP32 step of the compensated path. The state is hi + lo per component;
-// the RK4 stages run in float on hi alone, and the increment h/6 (k1 + 2 k2 +
-// 2 k3 + k4) is added to hi + lo with an error-free TwoSum, so the state keeps
-// about twice float precision while the right-hand sides are evaluated in
-// float. (s, c) = sin/cos(hi.th) on entry and exit. The proposal is accepted
-// only when it stays inside [0, pi] and satisfies |xi + 1| <= guard (in float,
-// guard < epsilon of eq. 4); otherwise the step returns -2 with the state
-// unchanged and the caller redoes it in FP64, so that every Euler-fallback
-// and remap decision of eq. (3)-(4) is taken in double precision.
-template <class T = float>
-GRAY_HD int rk4_step_c32(const StepConst<float> &K, State<float> &hi, State<float> &lo, float &s,
-                         float &c, float guard)
-{
-    const float akr = fabsf(hi.kr);
-    const float D1 = fma(hi.r, fabsf(hi.kth) + fabsf(hi.kph), akr);
-    const float n1 = K.step_frac * hi.r;
-    const float n2 = hi.r - K.rbh;
-    const float d2 = akr + akr;
-    const bool second = (hi.kr != 0.0f) && (n2 * D1 < d2 * n1);
-    const float h = second ? quot(n2, d2) : quot(n1, D1);
-    const bool hbad = !(h > 0.0f && h < INFINITY);
-    const float hh = 0.5f * h;
-
-    State<float> k1, k2, k3, k4, y;
-    float sy, cy;
-    deriv(K.B, hi, s, c, k1);
-    y = axpy(hi, hh, k1);
-    shift_sincos(s, c, y.th - hi.th, y.th, sy, cy);
-    deriv(K.B, y, sy, cy, k2);
-    y = axpy(hi, hh, k2);
-    shift_sincos(s, c, y.th - hi.th, y.th, sy, cy);
-    deriv(K.B, y, sy, cy, k3);
-    y = axpy(hi, h, k3);
-    shift_sincos(s, c, y.th - hi.th, y.th, sy, cy);
-    deriv(K.B, y, sy, cy, k4);
-
-    const float h6 = h * (1.0f / 6.0f);
-    State<float> nh, nl;
-#define GRAY_C32(cmp) two_sum(hi.cmp, fma(h6, k1.cmp + 2.0f * (k2.cmp + k3.cmp) + k4.cmp, lo.cmp), nh.cmp, nl.cmp)
-    GRAY_C32(t); GRAY_C32(r); GRAY_C32(th); GRAY_C32(ph);
-    GRAY_C32(kt); GRAY_C32(kr); GRAY_C32(kth); GRAY_C32(kph);
-#undef GRAY_C32
-    // every rejection in one wave-wide test (an invalid h computes the
-    // stages on non-finite values and is rejected here)
-    sin_cos(nh.th, sy, cy);
-    const bool reject = hbad || !(nh.th >= 0.0f && nh.th <= float(kPi)) ||
-                        !(__builtin_isfinite(nh.t) && __builtin_isfinite(nh.r) && __builtin_isfinite(nh.ph) && __builtin_isfinite(nh.kt) &&
-                          __builtin_isfinite(nh.kr) && __builtin_isfinite(nh.kth) && __builtin_isfinite(nh.kph)) ||
-                        xi_violated_at(K.B.a, K.B.a2, nh.r, sy, cy, nh.kt, nh.kr, nh.kth, nh.kph, guard);
-    if (__builtin_expect(any_lane(reject), 0))
-        if (reject) return -2;
-    hi = nh;
-    lo = nl;
-    s = sy;
-    c = cy;
-    return 0;
 }
 
 // The null monitor of eq. (4) in float with a bound on its own rounding:

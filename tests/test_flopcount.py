@@ -23,4 +23,4 @@ def test_flop_count_matches_benchmark_constant(tmp_path):
     out = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
     assert out["flags"] == 0
     assert out["step_flops"] == bench.F_STEP["fp64"]
-    assert out["rhs_flops"] > 100
+    assert 80 < out["rhs_flops"] < out["step_flops"] / 4
