@@ -284,8 +284,12 @@ int gray_camera_init_slot(const gray_camera *cams, int32_t ncam, int32_t slot,
  * queue. Without GRAY_WORKLIST the queue holds the running photons ordered
  * so that those expected to take the most steps (constants of motion near a
  * spherical photon orbit, or small |L_z|: paths near the polar axis) start
- * first; the order never changes a photon's result. Resumable: the state is the checkpoint, and repeated calls
- * with call_steps > 0 reproduce a single call exactly (bit for bit in FP64).
+ * first; the order never changes a photon's result. Resumable: the state is
+ * the checkpoint, and repeated calls with call_steps > 0 reproduce a single
+ * call bit for bit (in GRAY_FP32C too: its FP64 steps round the state to
+ * the float pair it is stored as). A time-bounded call is expressed as this
+ * step budget rather than a time limit, so that where a photon pauses never
+ * depends on timing.
  * workspace: device memory of gray_workspace_size() bytes, 256-byte aligned. */
 int gray_integrate(const gray_camera *cams, int32_t ncam, const gray_params *p,
                    gray_state *s, void *workspace, size_t workspace_bytes, void *hip_stream);

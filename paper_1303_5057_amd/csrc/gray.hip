@@ -641,7 +641,10 @@ struct StopBook {
 // the polar axis (the production monitor unless a caller asks for one of the
 // paper's earlier treatments), a template parameter so that the production
 // kernel carries no code for the others; MET selects the spacetime (Kerr, or
-// the deformed metric through the metric-generic right-hand side).
+// the deformed metric through the metric-generic right-hand side). The Kerr
+// kernel takes 135 vector registers, three waves per SIMD; it would fit in
+// 128 (four waves) without spilling, but measured slower that way (C2 +7%,
+// far-field steady state +3%, 256-camera sweep -0.4%).
 template <int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR>
 __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
@@ -657,8 +660,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     bool active = false;
     int64_t id = 0;
     Lane<GRAY_FP64> L;
+    // (the launch-wide constants are set once, so that they stay uniform)
     StepConst<double, Space> K;
-    double rcap = 0.0, resc = 0.0;
+    K.step_frac = A.step_frac;
+    K.xi_eps = A.xi_eps;
+    K.euler_inv = A.euler_inv;
+    const double resc = A.r_escape;
+    double rcap = 0.0;
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
 
@@ -730,11 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                         else
                             K.B = make_spin(cm.a);
                         K.rbh = cm.rbh;
-                        K.step_frac = A.step_frac;
-                        K.xi_eps = A.xi_eps;
-                        K.euler_inv = A.euler_inv;
                         rcap = cm.rcap;
-                        resc = A.r_escape;
                         nsteps = glob(PA.steps)[id];
                         ncall = 0;
                         ne = nr = n64 = 0;
@@ -921,7 +925,11 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
     bool active = false, pending = false;
     int64_t id = 0;
     Lane<GRAY_FP32C> L;
+    // (the launch-wide constants are set once, so that they stay uniform)
     StepConst<float> Kf;
+    Kf.step_frac = (float)A.step_frac;
+    Kf.xi_eps = (float)A.xi_eps;
+    Kf.euler_inv = (float)A.euler_inv;
     FloatHorizon Hf{};
     float r64 = 0.0f, rcap_f = 0.0f, rmark_f = 0.0f, rband_f = 0.0f;
     const float pole_f = (float)A.fp64_pole, turn_f = (float)A.fp64_turn;
@@ -985,9 +993,6 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
                         const DevCam cm = PA.cams[glob(PA.cam)[id]];
                         Kf.B = make_spin((float)cm.a);
                         Kf.rbh = (float)cm.rbh;
-                        Kf.step_frac = (float)A.step_frac;
-                        Kf.xi_eps = (float)A.xi_eps;
-                        Kf.euler_inv = (float)A.euler_inv;
                         Hf = make_float_horizon(cm.a);
                         r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
                         rcap_f = (float)(cm.rcap * (1.0 + 1e-6));
@@ -1158,7 +1163,11 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
     int64_t id = 0;
     State<double> x{};   // always a sum hi + lo of two floats
     double s64 = 0.0, c64 = 1.0;   // sin and cos of x.th
+    // (the launch-wide constants are set once, so that they stay uniform)
     StepConst<double, Spin<double>> K;
+    K.step_frac = A.step_frac;
+    K.xi_eps = A.xi_eps;
+    K.euler_inv = A.euler_inv;
     double rcap = 0.0;
     int32_t nsteps = 0, ncall = 0, ne = 0, nr = 0, n64 = 0;
     bool hit = false;
@@ -1205,9 +1214,6 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
                     const DevCam cm = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
                     K.B = make_spin(cm.a);
                     K.rbh = cm.rbh;
-                    K.step_frac = A.step_frac;
-                    K.xi_eps = A.xi_eps;
-                    K.euler_inv = A.euler_inv;
                     rcap = cm.rcap;
                     active = true;
                 }
@@ -1292,10 +1298,13 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
     }
 }
 
-// Three waves per SIMD (at most 168 vector registers): the FP64 loop alone
-// would take 174, and the few it gives up are spilled on the recorder's
-// event path only.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_integrate_c32(IntArgs A)
+// Four waves per SIMD (at most 128 vector registers). The float loop fits;
+// the FP64 loop keeps a few values in scratch memory, which costs its steps
+// less than the fourth wave gains the float ones (against three waves per
+// SIMD and no spills in its steps: far-field steady state -12%, 2048^2 of the
+// 4096^2 recorder workload -14%, 256-camera sweep -9%, the 512^2 edge-on grid,
+// bound by one photon in the FP64 loop, +3%).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_integrate_c32(IntArgs A)
 {
     __shared__ HandQueue Q;
     constexpr unsigned kWaves = kBlock / kWave;
