@@ -24,6 +24,12 @@
  *     GRAY_EDEVICE; gray_strerror() then describes it. Numerical failure is
  *     per photon (status GRAY_NONFINITE), never a call error.
  *   - n == 0 is valid and enqueues nothing.
+ *   - Shape of the interface: gray_camera_init needs no workspace;
+ *     gray_integrate takes its workspace with its size; every per-photon
+ *     array, outputs included (counters, mark, disk record), lives in
+ *     gray_state; a time-bounded integrate call is a step budget
+ *     (gray_params.call_steps), and a running call can be stopped early
+ *     through gray_state.stop.
  *
  * Photon state (gray_state), structure of arrays in device memory
  *   x      component-major, 8 rows of `stride` elements:
@@ -241,6 +247,22 @@ typedef struct {
                              photon (each advances every busy lane by one
                              step); the caller zeroes it. Lane efficiency of
                              a call = photon-steps / (64 * wave_iters)       */
+    const uint32_t *stop; /* optional [1]: a stop request to a running
+                             gray_integrate (a watchdog), in device memory or
+                             in host memory mapped for the device (the
+                             library reads it past the caches and never
+                             writes it). Each wave reads it every 64 of its
+                             loop iterations; once it reads non-zero, every
+                             photon the wave holds or takes from then on is
+                             stored after its next step, as at the end of
+                             call_steps (GRAY_RUNNING unless that step ended
+                             it; in work-list mode it goes on to work_out),
+                             so the call ends after about one step per
+                             remaining photon. In GRAY_FP32C a photon that
+                             needs an FP64 step is stored without taking it,
+                             and photons already handed to their block's
+                             FP64 wave run to their end. A later call
+                             continues every photon bit for bit.           */
 } gray_state;
 
 /* Outputs of gray_classify, all device memory, all rows `stride` apart

@@ -383,6 +383,7 @@ struct IntArgs {
     int32_t two_ended;          // odd wave slots take ids from the end of the queue
     int32_t helper;             // FP32C: the FP64 wave may run float photons
     int32_t pad;
+    const unsigned *stop;       // host-set stop request, or null
 };
 
 // Argument block fields of the running k_integrate, read again where they
@@ -632,6 +633,43 @@ struct StopBook {
     }
 };
 
+// One grab from the two-ended queue of ids: one atomic on the (head, tail)
+// pair. With h ids taken from the head and t from the tail before this grab,
+// the free positions are [h, nq - t): a head grab takes the first `grab` of
+// them, a tail grab the last; every position is handed out exactly once, and
+// the grab that brings h + t to nq or beyond (and every later one) finds the
+// queue empty. The wave's chunk becomes [chunk_next, chunk_end). Wave-uniform.
+__device__ __forceinline__ void queue_grab(unsigned lane, bool from_tail, unsigned grab, int64_t nq,
+                                           bool &exhausted, unsigned &chunk_next, unsigned &chunk_end)
+{
+    unsigned long long old = 0;
+    if (lane == 0)
+        old = atomicAdd(GRAY_ARG(queue), from_tail ? (unsigned long long)grab << 32 : (unsigned long long)grab);
+    const int64_t h = __builtin_amdgcn_readfirstlane((unsigned)old);
+    const int64_t t = __builtin_amdgcn_readfirstlane((unsigned)(old >> 32));
+    const int64_t end = nq - t;
+    if (h + t + grab >= nq) exhausted = true;
+    int64_t lo = h, hi = h;
+    if (end > h) {
+        if (from_tail) {
+            hi = end;
+            lo = end - grab > h ? end - grab : h;
+        } else {
+            hi = h + grab < end ? h + grab : end;
+        }
+    }
+    chunk_next = (unsigned)lo;
+    chunk_end = (unsigned)hi;
+}
+
+// The host-set stop request (gray_state::stop, non-null), read past the
+// caches. Wave-uniform.
+__device__ __forceinline__ bool stop_requested()
+{
+    const unsigned v = __hip_atomic_load((unsigned *)GRAY_ARG(stop), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return __builtin_amdgcn_readfirstlane(v) != 0u;
+}
+
 // Persistent integrator (FP64). Each wave keeps 64 photons in registers;
 // whenever at least A.refill lanes are idle it hands them the next photons of
 // the wave's current chunk of the queue, taking a new chunk from the global
@@ -641,11 +679,13 @@ struct StopBook {
 // the polar axis (the production monitor unless a caller asks for one of the
 // paper's earlier treatments), a template parameter so that the production
 // kernel carries no code for the others; MET selects the spacetime (Kerr, or
-// the deformed metric through the metric-generic right-hand side). The Kerr
+// the deformed metric through the metric-generic right-hand side). Every
+// wave reads the host's stop request (if any) every 64 loop iterations and,
+// once it is set, stores the photons it holds and leaves. The Kerr
 // kernel takes 135 vector registers, three waves per SIMD; it would fit in
 // 128 (four waves) without spilling, but measured slower that way (C2 +7%,
 // far-field steady state +3%, 256-camera sweep -0.4%).
-template <int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR>
+template <int PM = kPoleMonitor, int MET = GRAY_METRIC_KERR, bool STOP = false>
 __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
 {
     static_assert(MET == GRAY_METRIC_KERR || PM == kPoleMonitor,
@@ -692,36 +732,33 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
     const unsigned grab = (unsigned)rounds * kQueueChunk;
     StopBook book;
     unsigned long long iters = 0;
+    const bool watch = STOP && A.stop != nullptr;
+    unsigned poll = 0;
+    bool halt = false;
+    // state, status, step count and counters of the photon that stops (or
+    // pauses) in this lane
+    auto store_photon = [&](int32_t st) {
+        const ArgPointers PA = arg_pointers<1>();
+        const int64_t S = A.stride;
+        L.store(PA.x, PA.lo, S, id);
+        glob(PA.status)[id] = st;
+        glob(PA.steps)[id] = nsteps;
+        if (PA.counters) {
+            Column<int32_t> C(PA.counters, S, id);
+            C.put(ne);
+            C.next();
+            C.put(nr);
+            C.next();
+            C.put(n64);
+        }
+    };
 
     for (;;) {
+        if (watch && !halt && (poll++ & 63u) == 0u) halt = stop_requested();
         const uint64_t idle = ballot(!active);
         if (__popcll(idle) >= A.refill || idle == ~0ull) {
-            if (chunk_next >= chunk_end && !exhausted) {
-                // One atomic on the (head, tail) pair. With h ids taken from
-                // the head and t from the tail before this grab, the free
-                // positions are [h, nq - t): a head grab takes the first
-                // `grab` of them, a tail grab the last; every position is
-                // handed out exactly once, and the grab that brings h + t to
-                // nq or beyond (and every later one) finds the queue empty.
-                unsigned long long old = 0;
-                if (lane == 0)
-                    old = atomicAdd(GRAY_ARG(queue), from_tail ? (unsigned long long)grab << 32 : (unsigned long long)grab);
-                const int64_t h = __builtin_amdgcn_readfirstlane((unsigned)old);
-                const int64_t t = __builtin_amdgcn_readfirstlane((unsigned)(old >> 32));
-                const int64_t end = nq - t;
-                if (h + t + grab >= nq) exhausted = true;
-                int64_t lo = h, hi = h;
-                if (end > h) {
-                    if (from_tail) {
-                        hi = end;
-                        lo = end - grab > h ? end - grab : h;
-                    } else {
-                        hi = h + grab < end ? h + grab : end;
-                    }
-                }
-                chunk_next = (unsigned)lo;
-                chunk_end = (unsigned)hi;
-            }
+            if (chunk_next >= chunk_end && !exhausted)
+                queue_grab(lane, from_tail, grab, nq, exhausted, chunk_next, chunk_end);
             const unsigned avail = chunk_end - chunk_next;
             if (avail > 0) {
                 const unsigned rank = lane_rank(idle);
@@ -812,21 +849,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
             ncall += ok;
             ne += ok ? (fl & 1) : 0;
             nr += ok ? ((fl >> 1) & 1) : 0;
-            const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
+            // (after a stop request every photon pauses after its next step)
+            const bool stop = halt || st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
             if (__builtin_expect(any_lane(stop), 0) && stop) {
-                const ArgPointers PA = arg_pointers<1>();
-                const int64_t S = A.stride;
-                L.store(PA.x, PA.lo, S, id);
-                glob(PA.status)[id] = st;
-                glob(PA.steps)[id] = nsteps;
-                if (PA.counters) {
-                    Column<int32_t> C(PA.counters, S, id);
-                    C.put(ne);
-                    C.next();
-                    C.put(nr);
-                    C.next();
-                    C.put(n64);
-                }
+                store_photon(st);
                 stop_now = true;
                 keep = st == GRAY_RUNNING;
                 active = false;
@@ -870,6 +896,7 @@ struct HandQueue {
     unsigned head;        // slots taken by the FP64 wave (monotonic)
     unsigned tail;        // slots reserved by the float waves (monotonic)
     unsigned float_done;  // float waves of the block that have exited
+    unsigned halt;        // a float wave of the block has seen a stop request
     unsigned ready[kHandCap];
     int32_t id[kHandCap], nsteps[kHandCap], ncall[kHandCap], ne[kHandCap], nr[kHandCap], n64[kHandCap],
         hit[kHandCap];
@@ -904,6 +931,7 @@ __device__ __forceinline__ void c32_store(const Lane<GRAY_FP32C> &L, int64_t id,
 // What a wave keeps from one phase to the next.
 struct WaveCtx {
     bool exhausted = false;        // the global queue has nothing left for it
+    bool halt = false;             // the host's stop request has been seen
     unsigned long long iters = 0;  // loop iterations with a stepping lane
     StopBook book;
 };
@@ -913,7 +941,7 @@ struct WaveCtx {
 // helper (HELPER): it takes ids only as many as it has idle lanes and only
 // while fewer than kHelperLimit photons wait for FP64, and the phase ends
 // once its lanes are empty.
-template <bool HELPER>
+template <bool HELPER, bool STOP>
 __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, unsigned nfloat_waves, WaveCtx &W)
 {
     const unsigned lane = threadIdx.x & (kWave - 1);
@@ -950,8 +978,18 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
     rounds = rounds < 1 ? 1 : (rounds > kMaxGrab ? kMaxGrab : rounds);
     StopBook &book = W.book;
     unsigned long long &iters = W.iters;
+    const bool watch = STOP && A.stop != nullptr;
+    unsigned poll = 0;
+    bool &halt = W.halt;
 
     for (;;) {
+        if (watch && !halt && (poll++ & 63u) == 0u) {
+            halt = stop_requested();
+            if (halt) {
+                if (HELPER) exhausted = true;   // the FP64 wave takes no more float work
+                else if (lane == 0) lds_store(&Q.halt, 1u);   // for the block's FP64 wave
+            }
+        }
         const uint64_t idle = ballot(!active);
         // the helper takes float work only while few photons wait for it
         const bool may_take = !HELPER || lds_load(&Q.tail) - lds_load(&Q.head) < kHelperLimit;
@@ -960,26 +998,8 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
             // a helper grabs as many ids as it has idle lanes, so it leaves
             // no ids behind when its phase ends
             const unsigned grab = HELPER ? (unsigned)__popcll(idle) : (unsigned)rounds * kQueueChunk;
-            if (chunk_next >= chunk_end && !exhausted && may_take) {
-                unsigned long long old = 0;
-                if (lane == 0)
-                    old = atomicAdd(GRAY_ARG(queue), from_tail ? (unsigned long long)grab << 32 : (unsigned long long)grab);
-                const int64_t h = __builtin_amdgcn_readfirstlane((unsigned)old);
-                const int64_t t = __builtin_amdgcn_readfirstlane((unsigned)(old >> 32));
-                const int64_t end = nq - t;
-                if (h + t + grab >= nq) exhausted = true;
-                int64_t lo = h, hi = h;
-                if (end > h) {
-                    if (from_tail) {
-                        hi = end;
-                        lo = end - grab > h ? end - grab : h;
-                    } else {
-                        hi = h + grab < end ? h + grab : end;
-                    }
-                }
-                chunk_next = (unsigned)lo;
-                chunk_end = (unsigned)hi;
-            }
+            if (chunk_next >= chunk_end && !exhausted && may_take)
+                queue_grab(lane, from_tail, grab, nq, exhausted, chunk_next, chunk_end);
             const unsigned avail = chunk_end - chunk_next;
             if (avail > 0) {
                 const unsigned rank = lane_rank(idle);
@@ -1089,7 +1109,8 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
                 ncall += ok;
                 ne += ok ? (fl & 1) : 0;
                 nr += ok ? ((fl >> 1) & 1) : 0;
-                const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
+                // (after a stop request every photon pauses after its next step)
+                const bool stop = halt || st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
                 if (__builtin_expect(any_lane(stop), 0) && stop) {
                     c32_store(L, id, st, nsteps, ne, nr, n64, A.stride);
                     stop_now = true;
@@ -1097,6 +1118,13 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
                     active = false;
                 }
             }
+        }
+        // After a stop request a photon that needs FP64 is stored as it
+        // stands (its step not taken) instead of handed over.
+        if (__builtin_expect(halt, 0) && active && pending) {
+            c32_store(L, id, GRAY_RUNNING, nsteps, ne, nr, n64, A.stride);
+            stop_now = keep = true;
+            active = pending = false;
         }
         book.account(stop_now, keep, id, lane, list_out, count_done);
 
@@ -1148,9 +1176,11 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
 // waves, FP64 steps on the compensated pair until they stop. Each step
 // rounds the state to 48-bit significands, which the float pair holds
 // exactly, and takes its sin/cos there, so a resumed call (which rebuilds
-// the state from the pair) continues bit for bit. Returns true when the wave is done (the float waves of its block
-// have exited and every handed-over photon has stopped), false when it has
-// nothing to do but the global queue may still hold float work.
+// the state from the pair) continues bit for bit. Returns true when the wave
+// is done (the float waves of its block have exited and every handed-over
+// photon has stopped or paused), false when it has nothing to do but the
+// global queue may still hold float work.
+template <bool STOP>
 __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, unsigned nfloat_waves, WaveCtx &W)
 {
     const unsigned lane = threadIdx.x & (kWave - 1);
@@ -1188,6 +1218,9 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
         ++tick;
         if (idle && !closed && (idle == ~0ull || __popcll(idle) >= kWave / 4 || (tick & 3u) == 0u)) {
             const unsigned done = __hip_atomic_load(&Q.float_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // after a stop request (seen by the block's float waves) this wave
+            // takes no more float work
+            if (STOP && __builtin_amdgcn_readfirstlane(lds_load(&Q.halt)) != 0u) W.exhausted = true;
             const unsigned h = __builtin_amdgcn_readfirstlane(lds_load(&Q.head));
             const unsigned t = __builtin_amdgcn_readfirstlane(lds_load(&Q.tail));
             // slots h, h + 1, ... that are published, as many as lanes are idle
@@ -1304,6 +1337,7 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
 // SIMD and no spills in its steps: far-field steady state -12%, 2048^2 of the
 // 4096^2 recorder workload -14%, 256-camera sweep -9%, the 512^2 edge-on grid,
 // bound by one photon in the FP64 loop, +3%).
+template <bool STOP = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_integrate_c32(IntArgs A)
 {
     __shared__ HandQueue Q;
@@ -1313,15 +1347,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         Q.head = 0u;
         Q.tail = 0u;
         Q.float_done = 0u;
+        Q.halt = 0u;
     }
     __syncthreads();
     const unsigned lane = threadIdx.x & (kWave - 1);
     WaveCtx W;
     if (threadIdx.x / kWave == kWaves - 1) {
-        while (!c32_fp64_phase(A, Q, kWaves - 1, W) && A.helper) c32_float_phase<true>(A, Q, kWaves - 1, W);
+        while (!c32_fp64_phase<STOP>(A, Q, kWaves - 1, W) && A.helper)
+            c32_float_phase<true, STOP>(A, Q, kWaves - 1, W);
         W.book.finish(lane, A.work_out != nullptr, W.iters);
     } else {
-        c32_float_phase<false>(A, Q, kWaves - 1, W);
+        c32_float_phase<false, STOP>(A, Q, kWaves - 1, W);
     }
 }
 
@@ -1596,8 +1632,32 @@ static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool sl
 }
 
 // Integrator variants: FP64 with each pole treatment, FP32C (production
-// treatment only), FP64 in the deformed metric (production treatment only).
+// treatment only), FP64 in the deformed metric (production treatment only);
+// each in a second build that honours gray_state::stop (its test costs the
+// loop 1-4%, so a call without a stop flag runs the build without it).
 constexpr int kVariants = 5;
+
+template <bool STOP>
+static void variant_kernels(const void *k[kVariants])
+{
+    k[0] = (const void *)k_integrate<kPoleMonitor, GRAY_METRIC_KERR, STOP>;
+    k[1] = (const void *)k_integrate_c32<STOP>;
+    k[2] = (const void *)k_integrate<kPoleEulerCrossing, GRAY_METRIC_KERR, STOP>;
+    k[3] = (const void *)k_integrate<kPoleNone, GRAY_METRIC_KERR, STOP>;
+    k[4] = (const void *)k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED, STOP>;
+}
+
+template <bool STOP>
+static void launch_variant(int variant, unsigned grid, hipStream_t st, const IntArgs &A)
+{
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((k_integrate<kPoleMonitor, GRAY_METRIC_KERR, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 1: hipLaunchKernelGGL((k_integrate_c32<STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 2: hipLaunchKernelGGL((k_integrate<kPoleEulerCrossing, GRAY_METRIC_KERR, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case 3: hipLaunchKernelGGL((k_integrate<kPoleNone, GRAY_METRIC_KERR, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    default: hipLaunchKernelGGL((k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    }
+}
 static int variant_of(const gray_params *p, int metric)
 {
     if (metric == GRAY_METRIC_DEFORMED) return 4;
@@ -1606,7 +1666,7 @@ static int variant_of(const gray_params *p, int metric)
 
 struct DeviceInfo {
     int cus = 0;
-    int blocks_per_cu[kVariants] = {0, 0, 0, 0, 0};
+    int blocks_per_cu[2][kVariants] = {};   // [honours the stop flag][variant]
 };
 static std::mutex g_dev_mutex;
 static DeviceInfo g_dev[64];
@@ -1623,16 +1683,16 @@ static int device_info(DeviceInfo &out)
         int cus = 0;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return device_error("hipDeviceGetAttribute", e);
-        const void *kernels[kVariants] = {
-            (const void *)k_integrate<kPoleMonitor>, (const void *)k_integrate_c32,
-            (const void *)k_integrate<kPoleEulerCrossing>, (const void *)k_integrate<kPoleNone>,
-            (const void *)k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED>};
-        for (int v = 0; v < kVariants; ++v) {
-            int nb = 0;
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[v], kBlock, 0);
-            if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
-            d.blocks_per_cu[v] = nb > 0 ? nb : 1;
-        }
+        const void *kernels[2][kVariants];
+        variant_kernels<false>(kernels[0]);
+        variant_kernels<true>(kernels[1]);
+        for (int w = 0; w < 2; ++w)
+            for (int v = 0; v < kVariants; ++v) {
+                int nb = 0;
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[w][v], kBlock, 0);
+                if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
+                d.blocks_per_cu[w][v] = nb > 0 ? nb : 1;
+            }
         d.cus = cus;
     }
     out = d;
@@ -1849,6 +1909,7 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     }
     A.cam_done = s->cam_done;
     A.wave_iters = (unsigned long long *)s->wave_iters;
+    A.stop = s->stop;
     A.n = s->n;
     A.stride = s->stride;
     A.step_frac = p->step_frac;
@@ -1863,7 +1924,8 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     A.flags = p->flags;
     A.refill = 1;
     const int variant = variant_of(p, metric);
-    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[variant];
+    const bool stop = s->stop != nullptr;
+    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[stop][variant];
     // FP32C: the FP64 wave of a block runs float photons while none waits
     // for it only when the launch is bound by throughput (work lists, or at
     // least kHelperPhotonsPerLane photons per float lane); a launch bound by
@@ -1874,16 +1936,10 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     // is capped at kMaxListWaves waves, which bounds the unused list tail.
     const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave)) : blocks_for(s->n);
     const unsigned grid = (unsigned)(need < resident ? need : resident);
-    switch (variant) {
-    case 0: hipLaunchKernelGGL((k_integrate<kPoleMonitor>), dim3(grid), dim3(kBlock), 0, st, A); break;
-    case 1: hipLaunchKernelGGL(k_integrate_c32, dim3(grid), dim3(kBlock), 0, st, A); break;
-    case 2: hipLaunchKernelGGL((k_integrate<kPoleEulerCrossing>), dim3(grid), dim3(kBlock), 0, st, A); break;
-    case 3: hipLaunchKernelGGL((k_integrate<kPoleNone>), dim3(grid), dim3(kBlock), 0, st, A); break;
-    default:
-        hipLaunchKernelGGL((k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED>), dim3(grid), dim3(kBlock), 0, st,
-                           A);
-        break;
-    }
+    if (stop)
+        launch_variant<true>(variant, grid, st, A);
+    else
+        launch_variant<false>(variant, grid, st, A);
     return check_launch("integrate launch");
 }
 

@@ -76,7 +76,7 @@ class gray_state(ctypes.Structure):
                 ("stride", ctypes.c_int64), ("work_in", ctypes.c_void_p),
                 ("work_out", ctypes.c_void_p), ("work_in_count", ctypes.c_void_p),
                 ("work_out_count", ctypes.c_void_p), ("cam_done", ctypes.c_void_p),
-                ("wave_iters", ctypes.c_void_p)]
+                ("wave_iters", ctypes.c_void_p), ("stop", ctypes.c_void_p)]
 
 
 class gray_result(ctypes.Structure):
@@ -263,6 +263,12 @@ class Batch:
 
     def set_call_steps(self, k: int) -> None:
         self.p.call_steps = int(k)
+
+    def set_stop_flag(self, ptr: Optional[int]) -> None:
+        """Address of a uint32 stop request (gray_state.stop) that integrate
+        calls read, or None: device memory, or host memory mapped for the
+        device."""
+        self.state.stop = ptr
 
     def camera_init(self, stream: Optional[int] = None) -> None:
         gray_camera_init(self.cam_arr, len(self.cams), self.p, self.state,

@@ -16,7 +16,12 @@ Between iterations the loop
     photons fit the pool (admission by HBM footprint; no bypass, so large
     requests are not starved),
   * sizes the next iteration's step budget (call_steps) so that an iteration
-    takes about `slice_ms`.
+    takes about `slice_ms`,
+  * cancels requests on demand: a waiting one leaves the queue; an admitted
+    one has its photons set to a terminal status behind the launch in flight
+    (the next launch drops them from the work list when it reads their
+    status), and its pool range is reused only after that launch, so no
+    stale list entry can reach a new request's photons.
 
 A photon's step is a function of its stored state alone, so a request's
 result does not depend on what else is in the pool or on how its steps are
@@ -85,6 +90,7 @@ class RequestResult:
     status: Optional[np.ndarray] = None
     x: Optional[np.ndarray] = None      # (8, n) final state (double; FP32C: hi + lo)
     steps: Optional[np.ndarray] = None
+    cancelled: bool = False             # cancelled before it finished (no results)
 
     @property
     def latency_s(self) -> float:
@@ -161,6 +167,9 @@ class Server:
         self.max_used = 0
         self.admit_order: List[int] = []
         self._gather: List[tuple] = []
+        # ranges of cancelled requests: (first, n, the launch that drops their
+        # photons from the work list); freed once that launch is enqueued
+        self._release_after: List[tuple] = []
 
     def _bind_work(self) -> None:
         """work_in = list `_cur` (read by the next integrate, appended to by
@@ -217,6 +226,34 @@ class Server:
         res.done_s = now
         return res
 
+    def _cancel(self, k: int, now: float) -> RequestResult:
+        """Cancel the request in slot k. Its photons are set to a terminal
+        status in stream order, behind the launch in flight; the next launch
+        reads that status for the ids still listed and drops them. The slot
+        is free at once (a photon that is not running is never counted);
+        the range only after that next launch."""
+        req, first, n, res, _ = self.active.pop(k)
+        self.status[first:first + n].fill_(G.UNFINISHED)
+        self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0.0)
+        self._release_after.append((first, n, self.iterations))
+        res.cancelled = True
+        res.done_s = now
+        return res
+
+    def _release_cancelled(self, idle: bool = False) -> None:
+        """Free the ranges whose photons no later launch can still list: those
+        of requests cancelled before the last enqueued launch, or every one
+        when the loop is idle (the input list is then emptied instead)."""
+        if idle and self._release_after:
+            self.work_count[self._cur].zero_()
+        keep = []
+        for first, n, launch in self._release_after:
+            if idle or launch < self.iterations:
+                self.alloc.release(first, n)
+            else:
+                keep.append((first, n, launch))
+        self._release_after = keep
+
     def _read_back(self) -> None:
         """Host copies of the retired requests' device results."""
         for res, dev in self._gather:
@@ -240,6 +277,7 @@ class Server:
         self.iterations += 1
         self.done_host[b].copy_(self.cam_done, non_blocking=True)
         self.done_event[b].record()
+        self._release_cancelled()
         return b
 
     def _wait(self, b: int, prev_done: Optional[float]) -> tuple:
@@ -257,12 +295,17 @@ class Server:
 
     # -------------------------------------------------------------- driver
     def run(self, requests: Sequence[Request], realtime: bool = True,
-            on_done=None) -> List[RequestResult]:
+            on_done=None, cancel: Optional[Dict[int, int]] = None) -> List[RequestResult]:
         """Serve `requests` (sorted by arrival). With realtime=False every
-        request is available at once (closed loop, for saturation)."""
+        request is available at once (closed loop, for saturation). `cancel`
+        maps request ids to a launch count: once that many launches have
+        been enqueued, the request is cancelled wherever it is (waiting or in
+        flight; a request already finished is not affected). Cancelled
+        requests are returned with `cancelled` set."""
         pending = list(requests)
         waiting: List[Request] = []
         done: List[RequestResult] = []
+        cancel = dict(cancel or {})
         t_start = time.perf_counter()
         i = 0
         # (count buffer, launch index) of the launch not yet read back
@@ -273,9 +316,22 @@ class Server:
             while i < len(pending) and (not realtime or pending[i].arrival_s <= now):
                 waiting.append(pending[i])
                 i += 1
+            for rid in [r for r, at in cancel.items() if at <= self.iterations]:
+                slot = next((k for k, a in self.active.items() if a[0].rid == rid), None)
+                w = next((r for r in waiting if r.rid == rid), None)
+                if slot is not None:
+                    done.append(self._cancel(slot, now))
+                elif w is not None:
+                    waiting.remove(w)
+                    done.append(RequestResult(w.rid, w.arrival_s, done_s=now, photons=w.camera.n,
+                                              cancelled=True))
+                elif any(r.rid == rid for r in pending[i:]):
+                    continue            # not arrived yet: cancelled on arrival
+                del cancel[rid]
             while waiting and self._admit(waiting[0], now):
                 waiting.pop(0)
             if not self.active:
+                self._release_cancelled(idle=True)
                 if i < len(pending):
                     time.sleep(max(0.0, pending[i].arrival_s - (time.perf_counter() - t_start)))
                 continue
@@ -319,7 +375,7 @@ def size_class(photons: int) -> str:
 
 
 def latency_stats(results: Sequence[RequestResult], skip: int = 0) -> dict:
-    rs = sorted(results, key=lambda r: r.rid)[skip:]
+    rs = [r for r in sorted(results, key=lambda r: r.rid)[skip:] if not r.cancelled]
     lat = np.array([r.latency_s for r in rs]) * 1e3
     steps = sum(r.photon_steps for r in rs)
     span = max(r.done_s for r in rs) - min(r.arrival_s for r in rs)

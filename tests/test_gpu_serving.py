@@ -63,3 +63,32 @@ def test_pool_reuse_after_retire():
     ref = out[0]
     for r in out[1:]:
         assert np.array_equal(r.x, ref.x) and np.array_equal(r.steps, ref.steps)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cancel_in_flight_and_waiting(prec):
+    """A request cancelled while its photons run leaves every other result
+    unchanged (bit for bit against a plain render of its camera), and its
+    pool range goes to the requests waiting behind it; a request cancelled
+    while waiting never runs."""
+    cams = [W.scaled(W.C2, 40, 32), W.scaled(W.C2, 48, 40), W.scaled(W.C1, 24, 24),
+            W.scaled(W.C2, 36, 30), W.scaled(W.C1, 20, 20)]
+    reqs = [W.Request(k, 0.0, c) for k, c in enumerate(cams)]
+    # the pool holds requests 0 and 1 only; 2-4 wait for a free range
+    cap = sum((c.n + 63) // 64 * 64 for c in cams[:2])
+    srv = Server(cap * bytes_per_photon(prec), W.Params(precision=prec), max_slots=4, slice_ms=1.0,
+                 keep_results=True)
+    out = {r.rid: r for r in srv.run(reqs, realtime=False, cancel={1: 2, 4: 0})}
+    print(f"cancel {prec}: admitted {srv.admit_order}, iterations {srv.iterations}", flush=True)
+    assert sorted(out) == list(range(5))
+    assert out[1].cancelled and out[4].cancelled
+    assert out[1].status is None and out[4].status is None
+    assert srv.admit_order == [0, 1, 2, 3]               # 4 never ran; 2 and 3 took 1's range
+    assert srv.max_used <= srv.capacity
+    for rid in (0, 2, 3):
+        m = out[rid]
+        assert not m.cancelled
+        st, steps, xf = _batch_render(cams[rid], prec)
+        assert np.array_equal(st, m.status)
+        assert np.array_equal(steps, m.steps)
+        assert np.array_equal(xf, m.x)
