@@ -207,8 +207,8 @@ typedef struct {
     /* GRAY_FP32C only: a photon continues in double precision from the
      * first step at which any of these holds (near the horizon, near a pole,
      * near a radial turning point); all >= 0, 0 disables a zone; e.g.
-     * 0.02, 0.05, 0 (float rounding near the horizon and the poles is
-     * amplified by 1/Delta and 1/sin^2 theta).                                */
+     * 0.02, 0, 0 (float rounding near the horizon is amplified by 1/Delta;
+     * the float step keeps its digits next to the poles without a zone).    */
     double fp64_horizon; /* r < r_bh (1 + fp64_horizon)                          */
     double fp64_pole;    /* sin(theta) < fp64_pole                                */
     double fp64_turn;    /* |k^r| < fp64_turn |k^t|                               */

@@ -66,9 +66,10 @@ class Params:
     record_disk: bool = False
     # FP32C: a photon continues in double precision once it comes near the
     # horizon, a pole or a radial turning point (r < r_bh (1 + fp64_horizon),
-    # sin(theta) < fp64_pole, |k^r| < fp64_turn |k^t|).
+    # sin(theta) < fp64_pole, |k^r| < fp64_turn |k^t|); only the horizon zone
+    # is on by default.
     fp64_horizon: float = 0.02
-    fp64_pole: float = 0.05
+    fp64_pole: float = 0.0
     fp64_turn: float = 0.0
     # treatment of the polar axis (Sec. 2): 0 the production null-condition
     # monitor, 1 the earlier Euler step on pole crossings, 2 none
