@@ -179,6 +179,13 @@ typedef struct {
     int32_t kind;      /* gray_camera_kind */
     int32_t metric;    /* gray_metric      */
     double deform;     /* deviation of GRAY_METRIC_DEFORMED; 0 for Kerr */
+    int32_t call_steps; /* >= 0; used by gray_integrate only when
+                           gray_params.call_steps > 0: if > 0, this camera's
+                           photons advance at most this many steps in the
+                           call instead of gray_params.call_steps (a serving
+                           loop gives a request whose last photons are
+                           running a larger budget); 0: gray_params'.     */
+    int32_t reserved;  /* 0 */
 } gray_camera;
 
 /* Treatment of steps near the polar axis, where Boyer-Lindquist coordinates

@@ -78,7 +78,9 @@ static_assert(sizeof(WsHeader) <= kWsHeader, "header fits its reserved space");
 
 // Per-camera constants the integrator needs, kept in the workspace.
 struct DevCam {
-    double a, a2, rbh, rcap, rmark, disk_rmin, disk_rmax, eps3;
+    double a, a2, rbh, rcap, disk_rmin, disk_rmax, eps3;
+    int32_t call_steps;   // per-camera step budget of a call (0: the call's)
+    int32_t pad;
 };
 static_assert(sizeof(DevCam) == 64, "DevCam is one 64-byte record");
 
@@ -777,7 +779,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntArgs A)
                         K.rbh = cm.rbh;
                         rcap = cm.rcap;
                         nsteps = glob(PA.steps)[id];
-                        ncall = 0;
+                        // a camera's own step budget counts against the
+                        // call's: ncall reaches call_steps after it
+                        ncall = cm.call_steps > 0 ? A.call_steps - cm.call_steps : 0;
                         ne = nr = n64 = 0;
                         if (PA.counters) {
                             Column<int32_t> C(PA.counters, S, id);
@@ -1016,11 +1020,13 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
                         Hf = make_float_horizon(cm.a);
                         r64 = (float)(cm.rbh * (1.0 + A.fp64_horizon));
                         rcap_f = (float)(cm.rcap * (1.0 + 1e-6));
-                        rmark_f = (float)cm.rmark;
-                        rband_f = (float)(cm.rmark * (1.0 + 2.0 * A.step_frac));
+                        rmark_f = (float)(2.0 * cm.rbh);
+                        rband_f = (float)(2.0 * cm.rbh * (1.0 + 2.0 * A.step_frac));
                         rcap = cm.rcap;
                         nsteps = glob(PA.steps)[id];
-                        ncall = 0;
+                        // a camera's own step budget counts against the
+                        // call's: ncall reaches call_steps after it
+                        ncall = cm.call_steps > 0 ? A.call_steps - cm.call_steps : 0;
                         Column<int32_t> C(PA.counters, S, id);
                         ne = C.get();
                         C.next();
@@ -1523,6 +1529,7 @@ static bool camera_physical_ok(const gray_camera &c)
     }
     if (!(c.r_obs > horizon_radius(c.a) && std::isfinite(c.r_obs))) return false;
     if (!(c.incl >= 0.0 && c.incl <= kPi)) return false;
+    if (c.call_steps < 0) return false;
     return std::isfinite(c.alpha_lo) && std::isfinite(c.alpha_hi) && std::isfinite(c.beta_lo) &&
            std::isfinite(c.beta_hi);
 }
@@ -1850,10 +1857,10 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
             d.a2 = c.a * c.a;
             d.rbh = horizon_radius(c.a);
             d.rcap = d.rbh * (1.0 + p->horizon_eps);
-            d.rmark = 2.0 * d.rbh;
             d.disk_rmin = p->disk_rmin < 0.0 ? isco_radius(c.a) : p->disk_rmin;
             d.disk_rmax = p->disk_rmax;
             d.eps3 = c.deform;
+            d.call_steps = c.call_steps;
         }
         hipLaunchKernelGGL(k_setup, dim3(1), dim3(kWave), 0, st, table, hdr,
                            wl ? s->work_out_count : (unsigned *)nullptr, ch);

@@ -54,7 +54,7 @@ class gray_camera(ctypes.Structure):
                 ("alpha_lo", ctypes.c_double), ("alpha_hi", ctypes.c_double),
                 ("beta_lo", ctypes.c_double), ("beta_hi", ctypes.c_double),
                 ("first", ctypes.c_int64), ("kind", ctypes.c_int32), ("metric", ctypes.c_int32),
-                ("deform", ctypes.c_double)]
+                ("deform", ctypes.c_double), ("call_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gray_params(ctypes.Structure):

@@ -16,7 +16,11 @@ Between iterations the loop
     photons fit the pool (admission by HBM footprint; no bypass, so large
     requests are not starved),
   * sizes the next iteration's step budget (call_steps) so that an iteration
-    takes about `slice_ms`,
+    takes about `slice_ms`, and gives a request whose last photons are
+    running (at most 1/64 of them, or 256) `tail_boost` times that budget:
+    those few photons then need fewer iterations to finish, while an
+    iteration's length is set by the pool's total work, not by the steps of
+    a few photons,
   * cancels requests on demand: a waiting one leaves the queue; an admitted
     one has its photons set to a terminal status behind the launch in flight
     (the next launch drops them from the work list when it reads their
@@ -112,6 +116,7 @@ class Server:
     slice_ms: float = 40.0
     keep_results: bool = False
     device: str = "cuda"
+    tail_boost: int = 8
 
     def __post_init__(self):
         import torch
@@ -161,6 +166,7 @@ class Server:
         self.alloc = RangeAllocator(S)
         self.stream = torch.cuda.current_stream().cuda_stream
         self.active: Dict[int, tuple] = {}     # slot -> (Request, first, n, RequestResult)
+        self._done_seen: Dict[int, int] = {}   # slot -> stopped photons in the last counts read
         self.call_steps = 64
         self.iterations = 0
         self.max_active = 0
@@ -199,6 +205,7 @@ class Server:
         res = RequestResult(req.rid, req.arrival_s, admit_s=now, photons=n)
         # the first launch that includes the request
         self.active[k] = (req, first, n, res, self.iterations)
+        self._done_seen[k] = 0
         self.admit_order.append(req.rid)
         self.max_active = max(self.max_active, len(self.active))
         self.max_used = max(self.max_used, self.alloc.used())
@@ -209,6 +216,7 @@ class Server:
         stream order (behind the launch still running) and read back once
         the loop ends, so retiring never waits for the GPU."""
         req, first, n, res, _ = self.active.pop(k)
+        self._done_seen.pop(k, None)
         torch = self.torch
         st = self.steps[first:first + n]
         dev = {"photon_steps": st.to(torch.int64).sum()}
@@ -233,6 +241,7 @@ class Server:
         is free at once (a photon that is not running is never counted);
         the range only after that next launch."""
         req, first, n, res, _ = self.active.pop(k)
+        self._done_seen.pop(k, None)
         self.status[first:first + n].fill_(G.UNFINISHED)
         self.slots[k] = G.gray_camera(0.0, 1000.0, 0.0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0.0)
         self._release_after.append((first, n, self.iterations))
@@ -270,6 +279,13 @@ class Server:
         of that copy. Nothing waits here."""
         b = self.iterations % 2
         self.p.call_steps = int(self.call_steps)
+        # tail budget, capped so that one photon's steps at about 2 us each
+        # take at most half a slice
+        tail = int(min(self.call_steps * self.tail_boost, self.slice_ms * 250.0))
+        for k, a in self.active.items():
+            n = a[2]
+            left = n - self._done_seen.get(k, 0)
+            self.slots[k].call_steps = tail if left <= max(256, n // 64) else 0
         G.gray_integrate(self.slots, self.max_slots, self.p, self.state, self.ws_ptr, self.ws_bytes,
                          self.stream)
         self._cur = 1 - self._cur          # the ids still running are the next input
@@ -348,6 +364,8 @@ class Server:
             # request was in that launch (a reused slot still shows the
             # previous request's count until its own init runs)
             for k in list(self.active.keys()):
+                if self.active[k][4] <= prev[1]:
+                    self._done_seen[k] = int(counts[k])
                 if self.active[k][4] <= prev[1] and counts[k] == self.active[k][2]:
                     r = self._retire(k, now)
                     done.append(r)

@@ -42,7 +42,7 @@ def test_struct_layouts(lib):
     for k, t in enumerate((G.gray_camera, G.gray_params, G.gray_state, G.gray_result)):
         assert lib.gray_struct_size(k) == ctypes.sizeof(t)
     assert lib.gray_struct_size(99) == 0
-    assert ctypes.sizeof(G.gray_camera) == 88
+    assert ctypes.sizeof(G.gray_camera) == 96
 
 
 def test_strerror_and_version(lib):
@@ -128,6 +128,17 @@ def test_invalid_state_rejected(lib):
     arr[1].first = 0
     s = _state(128, 128)
     assert G.load().gray_camera_init(arr, 2, ctypes.byref(p), ctypes.byref(s), None) == G.GRAY_EINVAL
+
+
+def test_negative_camera_step_budget_rejected(lib):
+    p = G.params_struct(W.Params(call_steps=50))
+    arr = G.camera_array([CAM])
+    arr[0].call_steps = -1
+    s = _state(64, 64)
+    assert G.load().gray_camera_init(arr, 1, ctypes.byref(p), ctypes.byref(s), None) == G.GRAY_EINVAL
+    with pytest.raises(G.GrayError) as e:
+        G.gray_integrate(arr, 1, p, s, 0x1000, 1 << 20)
+    assert e.value.code == G.GRAY_EINVAL
 
 
 def test_fp32c_integrate_needs_counters(lib):

@@ -92,3 +92,39 @@ def test_cancel_in_flight_and_waiting(prec):
         assert np.array_equal(st, m.status)
         assert np.array_equal(steps, m.steps)
         assert np.array_equal(xf, m.x)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_per_camera_step_budget(prec):
+    """gray_camera.call_steps: a camera's own step budget replaces the call's
+    for its photons; resuming reproduces one uninterrupted call bit for bit."""
+    import torch
+    cams = [W.scaled(W.C2, 40, 32), W.scaled(W.C1, 24, 24)]
+    ref = G.Batch(cams, W.Params(precision=prec))
+    ref.camera_init()
+    ref.integrate()
+    torch.cuda.synchronize()
+    b = G.Batch(cams, W.Params(precision=prec, call_steps=50))
+    b.cam_arr[1].call_steps = 200
+    b.camera_init()
+    b.integrate()
+    torch.cuda.synchronize()
+    n0 = cams[0].n
+    steps = b.steps[: b.n].cpu().numpy()
+    st = b.status[: b.n].cpu().numpy()
+    print(f"budget {prec}: max steps {steps[:n0].max()} / {steps[n0:].max()}", flush=True)
+    assert steps[:n0].max() == 50 and steps[n0:].max() == 200
+    # a photon still running has taken exactly its camera's budget
+    assert (steps[:n0][st[:n0] == G.RUNNING] == 50).all()
+    assert (steps[n0:][st[n0:] == G.RUNNING] == 200).all()
+    for _ in range(200):
+        if not (b.status[: b.n] == G.RUNNING).any().item():
+            break
+        b.integrate()
+        torch.cuda.synchronize()
+    for name in ("status", "steps", "x"):
+        got = getattr(b, name)[: b.n] if name != "x" else b.x.view(8, b.stride)[:, : b.n]
+        want = getattr(ref, name)[: ref.n] if name != "x" else ref.x.view(8, ref.stride)[:, : ref.n]
+        assert torch.equal(got, want), name
+    if prec == "fp32c":
+        assert torch.equal(b.lo.view(8, b.stride)[:, : b.n], ref.lo.view(8, ref.stride)[:, : ref.n])
