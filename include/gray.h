@@ -267,8 +267,9 @@ typedef struct {
                              so the call ends after about one step per
                              remaining photon. In GRAY_FP32C a photon that
                              needs an FP64 step is stored without taking it,
-                             and photons already handed to their block's
-                             FP64 wave run to their end. A later call
+                             and the photons of a block's FP64 wave are
+                             stored after their next step once the block's
+                             float waves have exited. A later call
                              continues every photon bit for bit.           */
 } gray_state;
 

@@ -1185,7 +1185,11 @@ __device__ __forceinline__ void c32_float_phase(const IntArgs &A, HandQueue &Q, 
 // the state from the pair) continues bit for bit. Returns true when the wave
 // is done (the float waves of its block have exited and every handed-over
 // photon has stopped or paused), false when it has nothing to do but the
-// global queue may still hold float work.
+// global queue may still hold float work. Once nothing more can arrive the
+// wave finishes its photons in a loop of their steps alone: without the
+// queue's code around it the register allocator keeps the step's values in
+// place (in the polling loop it splits them around the hand-over, about 45
+// register copies per step), which is what a launch's last photons run.
 template <bool STOP>
 __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, unsigned nfloat_waves, WaveCtx &W)
 {
@@ -1211,68 +1215,12 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
     unsigned long long &iters = W.iters;
     // The queue is closed once the block's float waves have exited (every
     // slot they reserved is then published) and every slot has been taken:
-    // nothing more can arrive, and the wave stops polling.
-    bool closed = false;
+    // nothing more can arrive, and the wave leaves the polling loop for a
+    // loop of its own photons alone.
     unsigned tick = 0;
 
-    for (;;) {
-        const uint64_t idle = ballot(!active);
-        // Poll while the queue may still receive photons: whenever every lane
-        // or a quarter of the lanes are idle, otherwise every fourth
-        // iteration (a wave with few photons left spends little of its step
-        // on the queue's loads).
-        ++tick;
-        if (idle && !closed && (idle == ~0ull || __popcll(idle) >= kWave / 4 || (tick & 3u) == 0u)) {
-            const unsigned done = __hip_atomic_load(&Q.float_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            // after a stop request (seen by the block's float waves) this wave
-            // takes no more float work
-            if (STOP && __builtin_amdgcn_readfirstlane(lds_load(&Q.halt)) != 0u) W.exhausted = true;
-            const unsigned h = __builtin_amdgcn_readfirstlane(lds_load(&Q.head));
-            const unsigned t = __builtin_amdgcn_readfirstlane(lds_load(&Q.tail));
-            // slots h, h + 1, ... that are published, as many as lanes are idle
-            const bool rdy = lane < t - h && lds_load(&Q.ready[(h + lane) % kHandCap]) != 0u;
-            const uint64_t rm = ballot(rdy);
-            unsigned c = (unsigned)__ffsll((long long)~rm) - 1u;   // published prefix
-            c = c < (unsigned)__popcll(idle) ? c : (unsigned)__popcll(idle);
-            if (c > 0) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                const unsigned rank = lane_rank(idle);
-                const bool took = !active && rank < c;
-                if (took) {
-                    const unsigned s = (h + rank) % kHandCap;
-                    id = Q.id[s];
-                    nsteps = Q.nsteps[s];
-                    ncall = Q.ncall[s];
-                    ne = Q.ne[s];
-                    nr = Q.nr[s];
-                    n64 = Q.n64[s];
-                    hit = Q.hit[s] != 0;
-                    double *xp = &x.t;
-                    for (int k = 0; k < 8; ++k) xp[k] = (double)Q.hi[k][s] + (double)Q.lo[k][s];
-                    sin_cos<true>(x.th, s64, c64);
-                    const DevCam cm = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
-                    K.B = make_spin(cm.a);
-                    K.rbh = cm.rbh;
-                    rcap = cm.rcap;
-                    active = true;
-                }
-                // every read of the taken slots is done before they are freed
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                if (took) lds_store(&Q.ready[(h + rank) % kHandCap], 0u);
-                if (lane == 0) lds_store(&Q.head, h + c);
-            } else {
-                closed = done == nfloat_waves && h == t;
-                if (idle == ~0ull) {
-                    if (closed) return true;
-                    if (!W.exhausted && A.helper) return false;
-                    __builtin_amdgcn_s_sleep(2);
-                    continue;
-                }
-            }
-        } else if (closed && idle == ~0ull) {
-            return true;
-        }
-
+    // One step of every active lane; `halt` stores each after its step.
+    auto advance = [&](bool halt) __attribute__((always_inline)) {
         bool stop_now = false, keep = false;
         iters += ballot(active) != 0ull;
         if (active) {
@@ -1323,7 +1271,7 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
             ne += ok ? (fl & 1) : 0;
             nr += ok ? ((fl >> 1) & 1) : 0;
             n64 += ok;
-            const bool stop = st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
+            const bool stop = halt || st != GRAY_RUNNING || (A.call_steps > 0 && ncall >= A.call_steps);
             if (__builtin_expect(any_lane(stop), 0) && stop) {
                 Lane<GRAY_FP32C> P;
                 P.split(x);
@@ -1334,7 +1282,79 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
             }
         }
         book.account(stop_now, keep, id, lane, list_out, count_done);
+    };
+
+    for (;;) {
+        const uint64_t idle = ballot(!active);
+        // Poll while the queue may still receive photons: whenever every lane
+        // or a quarter of the lanes are idle, otherwise every fourth
+        // iteration (a wave with few photons left spends little of its step
+        // on the queue's loads).
+        ++tick;
+        if (idle && (idle == ~0ull || __popcll(idle) >= kWave / 4 || (tick & 3u) == 0u)) {
+            const unsigned done = __hip_atomic_load(&Q.float_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // after a stop request (seen by the block's float waves) this wave
+            // takes no more float work
+            if (STOP && __builtin_amdgcn_readfirstlane(lds_load(&Q.halt)) != 0u) W.exhausted = true;
+            const unsigned h = __builtin_amdgcn_readfirstlane(lds_load(&Q.head));
+            const unsigned t = __builtin_amdgcn_readfirstlane(lds_load(&Q.tail));
+            // slots h, h + 1, ... that are published, as many as lanes are idle
+            const bool rdy = lane < t - h && lds_load(&Q.ready[(h + lane) % kHandCap]) != 0u;
+            const uint64_t rm = ballot(rdy);
+            unsigned c = (unsigned)__ffsll((long long)~rm) - 1u;   // published prefix
+            c = c < (unsigned)__popcll(idle) ? c : (unsigned)__popcll(idle);
+            if (c > 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const unsigned rank = lane_rank(idle);
+                const bool took = !active && rank < c;
+                if (took) {
+                    const unsigned s = (h + rank) % kHandCap;
+                    id = Q.id[s];
+                    nsteps = Q.nsteps[s];
+                    ncall = Q.ncall[s];
+                    ne = Q.ne[s];
+                    nr = Q.nr[s];
+                    n64 = Q.n64[s];
+                    hit = Q.hit[s] != 0;
+                    double *xp = &x.t;
+                    for (int k = 0; k < 8; ++k) xp[k] = (double)Q.hi[k][s] + (double)Q.lo[k][s];
+                    sin_cos<true>(x.th, s64, c64);
+                    const DevCam cm = GRAY_ARG(cams)[glob(GRAY_ARG(cam))[id]];
+                    K.B = make_spin(cm.a);
+                    K.rbh = cm.rbh;
+                    rcap = cm.rcap;
+                    active = true;
+                }
+                // every read of the taken slots is done before they are freed
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (took) lds_store(&Q.ready[(h + rank) % kHandCap], 0u);
+                if (lane == 0) lds_store(&Q.head, h + c);
+            } else {
+                const bool closed = done == nfloat_waves && h == t;
+                if (idle == ~0ull) {
+                    if (closed) return true;
+                    if (!W.exhausted && A.helper) return false;
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
+                if (closed) break;
+            }
+        }
+
+        advance(false);
     }
+
+    // Tail: the queue is closed and only the wave's own photons remain. Here
+    // the wave reads the stop request itself (the flag of its block's float
+    // waves, then the host's every 64 iterations).
+    const bool watch = STOP && A.stop != nullptr;
+    bool halt = STOP && (W.halt || __builtin_amdgcn_readfirstlane(lds_load(&Q.halt)) != 0u);
+    unsigned poll = 0;
+    while (ballot(active) != 0ull) {
+        if (watch && !halt && (poll++ & 63u) == 0u) halt = stop_requested();
+        advance(halt);
+    }
+    return true;
 }
 
 // Four waves per SIMD (at most 128 vector registers). The float loop fits;
