@@ -6,8 +6,9 @@ A call that reads a set flag stores every photon after at most its next step
 photon bit for bit, so the final results equal those of one uninterrupted
 call. Covered: the flag set before the launch (dense and work-list mode) and
 set by the host while the kernel runs (the flag in host memory mapped for
-the device), in both precisions. Every kernel ends on its own either way;
-the flag only makes it end sooner.
+the device), in both precisions; in FP32C the photons of the FP64 waves are
+paused too. Every kernel ends on its own either way; the flag only makes it
+end sooner.
 """
 import ctypes
 import time
@@ -165,10 +166,18 @@ def test_stop_while_running(prec):
         word.value = 1
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        running = int((b.status[: b.n] == G.RUNNING).sum().item())
+        run_mask = b.status[: b.n] == G.RUNNING
+        running = int(run_mask.sum().item())
+        # photons paused after FP64 steps (FP32C: by the block's FP64 wave)
+        n64 = b.counters.view(3, b.stride)[2, : b.n]
+        paused64 = int((run_mask & (n64 > 0)).sum().item())
         print(f"stop while running {prec}: call ended after {1e3 * (t1 - t0):.2f} ms with {running} of "
-              f"{b.n} photons paused", flush=True)
+              f"{b.n} photons paused ({paused64} after FP64 steps)", flush=True)
         assert running > 0
+        if prec == "fp32c":
+            # the FP64 waves pause their photons too once their blocks' float
+            # waves have exited, instead of running them to their end
+            assert paused64 > 0
         word.value = 0
         _finish(b, "after a stop while running")
         _same(r, _outputs(b), f"{prec} resumed after a stop while running")
