@@ -29,11 +29,13 @@ sys.path.insert(0, ROOT)
 # path: RK4 + step size + null-condition check), weights add/mul 1, fma 2,
 # div/sqrt/sin/cos 1; produced by csrc/flopcount.cpp and checked by the tests.
 F_STEP = {"fp64": 538, "fp32c": 538}
-# MI355X published vector peaks, TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 flops
-# x 2.4 GHz). FP32 reaches 157.3 only with packed (two-per-lane) FP32
-# instructions, which this library does not use; its float code issues at the
-# FP64 rate, so both precisions are held to 78.6.
-PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 78.6}
+# MI355X published vector peaks, TFLOP/s: FP64 78.6 (256 CUs x 4 SIMDs x 16
+# lanes x 2 flops x 2.4 GHz), FP32 157.3 (twice that). The FP32C integrator is
+# held to the FP32 one: without packed FP32 a SIMD still issues FP32
+# instructions whose operands are all vector registers through a second VALU
+# path (measured with csrc/valu_peak.hip: non-packed FP32 FMA chains at 2.5
+# cycles per wave64 instruction, 126 TFLOP/s; FP64 at 4.1-4.8 cycles).
+PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 # Rays closer than this to the critical curve (M, on the ray's own constants of
 # motion) may legitimately differ in outcome between two correct integrators.
 BAND = 1e-3

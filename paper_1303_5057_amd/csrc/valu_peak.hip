@@ -1,6 +1,7 @@
 // Vector issue-rate probe for the roofline peaks of the integrators: each
 // thread runs 8 independent chains of one operation (FMA, multiply, add, or
-// two of them interleaved) in FP32 and FP64, non-packed (built, like the
+// two of them interleaved) in FP32 and FP64, with the other operands in
+// scalar or in vector registers, non-packed (built, like the
 // library, with packed FP32 disabled), and writes one value. Prints the
 // FLOP rate and the SIMD cycles per wave64 instruction (2.4 GHz, 1024 SIMDs).
 //   hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang -packed-fp32-ops \
@@ -8,9 +9,13 @@
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <vector>
-template <typename T, int OP>
-__global__ __launch_bounds__(256) void k_chains(T *out, int iters, T b, T c)
+template <typename T, int OP, bool V>
+__global__ __launch_bounds__(256) void k_chains(T *out, int iters, T bs, T cs)
 {
+    // V: the multiplier and addend in vector registers (per-lane values),
+    // else in scalar registers (kernel arguments)
+    const T b = V ? bs + (T)threadIdx.x * (T)1e-9 : bs;
+    const T c = V ? cs + (T)threadIdx.x * (T)1e-9 : cs;
     T a0 = (T)threadIdx.x * (T)1e-3, a1 = a0 + (T)1, a2 = a0 + (T)2, a3 = a0 + (T)3;
     T a4 = a0 + (T)4, a5 = a0 + (T)5, a6 = a0 + (T)6, a7 = a0 + (T)7;
     for (int i = 0; i < iters; ++i) {
@@ -36,7 +41,7 @@ __global__ __launch_bounds__(256) void k_chains(T *out, int iters, T b, T c)
     }
     out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
 }
-template <typename T, int OP>
+template <typename T, int OP, bool V = false>
 double run(const char *name, int blocks, int iters)
 {
     T *out;
@@ -48,7 +53,7 @@ double run(const char *name, int blocks, int iters)
     for (int r = 0; r < 6; ++r) {
         float ms = 0.0f;
         bool ok = hipEventRecord(e0, 0) == hipSuccess;
-        hipLaunchKernelGGL((k_chains<T, OP>), dim3(blocks), dim3(256), 0, 0, out, iters, (T)0.999, (T)1e-3);
+        hipLaunchKernelGGL((k_chains<T, OP, V>), dim3(blocks), dim3(256), 0, 0, out, iters, (T)0.999, (T)1e-3);
         ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, 0) == hipSuccess;
         ok = ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
         if (!ok) { printf("launch or timing failed\n"); return 0; }
@@ -83,5 +88,10 @@ int main()
     run<double, 3>("fp64 fma+mul", blocks, 4096);
     run<double, 4>("fp64 fma+add", blocks, 4096);
     run<double, 5>("fp64 mul+add", blocks, 4096);
+    run<float, 0, true>("fp32 fma, vector operands", blocks, 4096);
+    run<float, 1, true>("fp32 mul, vector operands", blocks, 4096);
+    run<float, 3, true>("fp32 fma+mul, vector operands", blocks, 4096);
+    run<double, 0, true>("fp64 fma, vector operands", blocks, 4096);
+    run<double, 1, true>("fp64 mul, vector operands", blocks, 4096);
     return 0;
 }
