@@ -1363,11 +1363,21 @@ __device__ __forceinline__ bool c32_fp64_phase(const IntArgs &A, HandQueue &Q, u
 // SIMD and no spills in its steps: far-field steady state -12%, 2048^2 of the
 // 4096^2 recorder workload -14%, 256-camera sweep -9%, the 512^2 edge-on grid,
 // bound by one photon in the FP64 loop, +3%).
-template <bool STOP = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_integrate_c32(IntArgs A)
+//
+// BLK: threads per block, each block one FP64 wave and BLK / 64 - 1 float
+// waves. Where the launch is bound by throughput, 512: a block of 448 float
+// lanes gives its FP64 wave about twice the photons that 192 do, and the
+// FP64 steps (a few percent of the steps there) cost about half as many wave
+// instructions (256-camera sweep -7%, 2048^2 of the 4096^2 recorder workload
+// -5%, far-field steady state unchanged). Where the launch is bound by its
+// longest photons, 256: the 512^2 edge-on grid takes a fifth of its steps in
+// FP64, which one wave per 448 float lanes cannot keep up with (+12-20%).
+template <bool STOP = false, int BLK = kBlock>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) void k_integrate_c32(IntArgs A)
 {
+    static_assert(BLK % kWave == 0 && BLK / kWave >= 2 && BLK >= kHandCap, "one FP64 wave, one float wave at least");
     __shared__ HandQueue Q;
-    constexpr unsigned kWaves = kBlock / kWave;
+    constexpr unsigned kWaves = BLK / kWave;
     if (threadIdx.x < (unsigned)kHandCap) Q.ready[threadIdx.x] = 0u;
     if (threadIdx.x == 0) {
         Q.head = 0u;
@@ -1662,7 +1672,10 @@ static bool fill_chunk(const gray_camera *cams, int32_t k0, int32_t cnt, bool sl
 // treatment only), FP64 in the deformed metric (production treatment only);
 // each in a second build that honours gray_state::stop (its test costs the
 // loop 1-4%, so a call without a stop flag runs the build without it).
-constexpr int kVariants = 5;
+constexpr int kVariants = 6;
+// FP32C block shapes (variant 1 and kVariantC32Wide)
+constexpr int kBlockC32Wide = 512;
+constexpr int kVariantC32Wide = 5;
 
 template <bool STOP>
 static void variant_kernels(const void *k[kVariants])
@@ -1672,7 +1685,9 @@ static void variant_kernels(const void *k[kVariants])
     k[2] = (const void *)k_integrate<kPoleEulerCrossing, GRAY_METRIC_KERR, STOP>;
     k[3] = (const void *)k_integrate<kPoleNone, GRAY_METRIC_KERR, STOP>;
     k[4] = (const void *)k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED, STOP>;
+    k[5] = (const void *)k_integrate_c32<STOP, kBlockC32Wide>;
 }
+static int variant_block(int variant) { return variant == kVariantC32Wide ? kBlockC32Wide : kBlock; }
 
 template <bool STOP>
 static void launch_variant(int variant, unsigned grid, hipStream_t st, const IntArgs &A)
@@ -1682,6 +1697,7 @@ static void launch_variant(int variant, unsigned grid, hipStream_t st, const Int
     case 1: hipLaunchKernelGGL((k_integrate_c32<STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
     case 2: hipLaunchKernelGGL((k_integrate<kPoleEulerCrossing, GRAY_METRIC_KERR, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
     case 3: hipLaunchKernelGGL((k_integrate<kPoleNone, GRAY_METRIC_KERR, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
+    case kVariantC32Wide: hipLaunchKernelGGL((k_integrate_c32<STOP, kBlockC32Wide>), dim3(grid), dim3(kBlockC32Wide), 0, st, A); break;
     default: hipLaunchKernelGGL((k_integrate<kPoleMonitor, GRAY_METRIC_DEFORMED, STOP>), dim3(grid), dim3(kBlock), 0, st, A); break;
     }
 }
@@ -1716,7 +1732,7 @@ static int device_info(DeviceInfo &out)
         for (int w = 0; w < 2; ++w)
             for (int v = 0; v < kVariants; ++v) {
                 int nb = 0;
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[w][v], kBlock, 0);
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernels[w][v], variant_block(v), 0);
                 if (e != hipSuccess) return device_error("hipOccupancyMaxActiveBlocksPerMultiprocessor", e);
                 d.blocks_per_cu[w][v] = nb > 0 ? nb : 1;
             }
@@ -1950,18 +1966,23 @@ static int integrate_checked(const gray_camera *cams, int32_t ncam, const gray_p
     A.call_steps = p->call_steps;
     A.flags = p->flags;
     A.refill = 1;
-    const int variant = variant_of(p, metric);
+    int variant = variant_of(p, metric);
     const bool stop = s->stop != nullptr;
-    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[stop][variant];
     // FP32C: the FP64 wave of a block runs float photons while none waits
     // for it only when the launch is bound by throughput (work lists, or at
     // least kHelperPhotonsPerLane photons per float lane); a launch bound by
     // its longest photons keeps it free, so that a long photon that goes
-    // over to FP64 is taken at once.
-    A.helper = wl || s->n >= kHelperPhotonsPerLane * resident * (kBlock - kWave);
+    // over to FP64 is taken at once. A launch bound by throughput also takes
+    // the wide block shape.
+    const bool throughput = wl || s->n >= kHelperPhotonsPerLane * (int64_t)dev.cus * dev.blocks_per_cu[stop][variant] *
+                                             (kBlock - kWave);
+    A.helper = throughput;
+    if (variant == 1 && throughput) variant = kVariantC32Wide;
+    const int blk = variant_block(variant);
+    const int64_t resident = (int64_t)dev.cus * dev.blocks_per_cu[stop][variant];
     // In work-list mode the list length is only known on the device; the grid
     // is capped at kMaxListWaves waves, which bounds the unused list tail.
-    const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (kBlock / kWave)) : blocks_for(s->n);
+    const int64_t need = wl ? std::min<int64_t>(resident, kMaxListWaves / (blk / kWave)) : (s->n + blk - 1) / blk;
     const unsigned grid = (unsigned)(need < resident ? need : resident);
     if (stop)
         launch_variant<true>(variant, grid, st, A);
